@@ -1,0 +1,261 @@
+/*
+ * hemelb_lb.h - C ABI of the sparse lattice-Boltzmann time step on MI355X (gfx950).
+ *
+ * The method (paper Section 2, "HemeLB model"): a lattice Boltzmann solver on a
+ * sparse lattice of fluid sites; each site holds one population per discrete
+ * lattice vector (D3Q19 in the paper, D3Q15 also supported), evolved by
+ * propagation (streaming) and collision steps, with Ladd velocity iolets at
+ * inlets and, in the experiments (Section 4), simple bounce-back at walls.
+ * Throughput is counted as in Table 3: site updates per second = fluid sites x
+ * steps / wall time.
+ *
+ * One step, as this library computes it, for every fluid site s and lattice
+ * direction i (upstream point y = x_s - c_i):
+ *   f_i(s) = A[i][y]                                   y fluid
+ *          = A[opp(i)][s]                              y wall (halfway bounce-back)
+ *          = f_i^eq(rho_k(t), u_s)                     y past pressure iolet k,
+ *                                                      u_s = velocity of A[:][s]
+ *          = A[opp(i)][s] + 6 w_i (c_i . e_k) U_k(t) W_s   y past velocity iolet k (Ladd)
+ *   rho = sum f, u = sum c f / rho,
+ *   f^eq_i(rho,u) = w_i rho (1 + 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u),
+ *   A'[i][s] = f_i - (f_i - f^eq_i(rho, (1 - alpha_s) u)) / tau.
+ * Step n (n = 1, 2, ...) uses boundary time t = n - 1.  The initial state is the
+ * rest equilibrium A = w_i.
+ *
+ * Lattice ordering (shared convention): index 0 is the rest vector, then
+ * opposite pairs (2k-1, 2k).
+ *   D3Q15: (+-1,0,0) (0,+-1,0) (0,0,+-1) +-(1,1,1) +-(1,1,-1) +-(1,-1,1) +-(-1,1,1)
+ *   D3Q19: (+-1,0,0) (0,+-1,0) (0,0,+-1) +-(1,1,0) +-(1,-1,0) +-(1,0,1) +-(1,0,-1)
+ *          +-(0,1,1) +-(0,1,-1)
+ * where "+-v" lists v then -v.
+ *
+ * Conventions for every call:
+ *   - return 0 on success, a negative HEMELB_E* code on failure; the calling
+ *     thread's message is available from hemelb_lb_last_error();
+ *   - "host" pointers are read (or written) before the call returns and stay
+ *     owned by the caller; "device" pointers are caller-owned device memory on
+ *     the handle's GPU, accessed asynchronously on the handle's stream;
+ *   - a handle is not thread-safe; separate handles are independent.
+ */
+#ifndef HEMELB_LB_H
+#define HEMELB_LB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hemelb_lb* hemelb_lb_t;
+
+/* error codes */
+#define HEMELB_OK 0
+#define HEMELB_EINVAL (-1)     /* invalid argument; nothing was done */
+#define HEMELB_ENOMEM (-2)     /* device or host allocation failed */
+#define HEMELB_EDEVICE (-3)    /* HIP runtime error (message holds the HIP string) */
+#define HEMELB_EDIVERGED (-4)  /* a divergence check found a non-finite density/momentum */
+#define HEMELB_EORDER (-5)     /* call out of order (e.g. adjoint without a forward tape) */
+#define HEMELB_ECANCELLED (-6) /* hemelb_lb_cancel() stopped a step request */
+
+/* population storage (the collision always computes in FP32) */
+#define HEMELB_STORE_F32 0  /* FP32 deviations f_i - w_i */
+#define HEMELB_STORE_F16 1  /* FP16 deviations, round-to-nearest-even */
+#define HEMELB_STORE_BF16 2 /* BF16 deviations, round-to-nearest-even */
+
+/* desc.flags */
+#define HEMELB_FLAG_NO_SCALE 1 /* 16-bit storage: omit the per-direction power-of-two scale */
+
+/* iolet kinds */
+#define HEMELB_IOLET_PRESSURE 0
+#define HEMELB_IOLET_VELOCITY 1
+
+/* upstream codes in the neighbour table */
+#define HEMELB_LINK_WALL (-1)           /* halfway bounce-back */
+#define HEMELB_LINK_IOLET(k) (-2 - (k)) /* upstream point lies past iolet k */
+
+/*
+ * Inlet/outlet ("iolet", paper Section 2 and Section 3.B: Ladd velocity iolets,
+ * with a velocity weights file and a time-dependent inlet velocity, Figure 6).
+ * The imposed value at boundary time t is
+ *   v(t) = mean + sum_{h=1..n_harm} cos_k[h-1] cos(2 pi h t / period)
+ *                                 + sin_k[h-1] sin(2 pi h t / period)
+ * and is a density (PRESSURE) or a speed along the unit vector `direction`
+ * (VELOCITY; the inward normal of an inlet, or a wall's tangential direction).
+ * cos_k / sin_k are host arrays of n_harm doubles (may be NULL when n_harm = 0).
+ */
+typedef struct {
+    int32_t kind;
+    double direction[3];
+    double mean;
+    int32_t n_harm;
+    const double* cos_k;
+    const double* sin_k;
+    double period;
+} hemelb_iolet_t;
+
+/*
+ * Problem description (paper Section 2: a sparse lattice of fluid sites and its
+ * boundary conditions; Table 1 / Section 4: step length, voxel size and
+ * viscosity fix the relaxation time tau; Table 2: site counts).
+ * All arrays are host memory, copied during hemelb_lb_create.
+ *   lattice      15 or 19
+ *   storage      HEMELB_STORE_*
+ *   flags        HEMELB_FLAG_*
+ *   n_sites      N >= 0 fluid sites (N + ghost links must stay below 2^30)
+ *   coords       int32 [N][3] site coordinates in [0, 2^21), or NULL.  When given,
+ *                sites are processed in Morton (Z-order, x lowest bit) order and the
+ *                wall normals can be derived; results still come back in caller order.
+ *   nbr          int32 [N][lattice]: nbr[s][i] = upstream code of direction i at
+ *                site s: a site index (>= 0), HEMELB_LINK_WALL, or HEMELB_LINK_IOLET(k).
+ *                Column 0 (rest) is ignored.  Fluid links must be reciprocal:
+ *                nbr[nbr[s][i]][opp(i)] == s.
+ *   tau          relaxation time, > 0.5; +infinity is accepted (no collision: a step
+ *                is then a pure permutation of the populations)
+ *   n_iolets, iolets
+ *   site_weight  double [N] inlet profile weight W_s, or NULL (all 1)
+ *   wall_normal  float [N][3] wall normals for the wall shear stress, or NULL
+ *                (normalize(sum of c_i over wall links i))
+ *   alpha        float [N] Brinkman damping in [0, 1], or NULL (0)
+ *   stream       hipStream_t for all work of the handle, or NULL (default stream)
+ */
+typedef struct {
+    int32_t lattice;
+    int32_t storage;
+    int32_t flags;
+    int64_t n_sites;
+    const int32_t* coords;
+    const int32_t* nbr;
+    double tau;
+    int32_t n_iolets;
+    const hemelb_iolet_t* iolets;
+    const double* site_weight;
+    const float* wall_normal;
+    const float* alpha;
+    void* stream;
+} hemelb_lb_desc_t;
+
+typedef struct {
+    int64_t n_sites;     /* N */
+    int64_t n_ghosts;    /* iolet links (one ghost population each) */
+    int64_t pitch;       /* elements between direction arrays of a population buffer */
+    int64_t time;        /* completed steps (boundary time of the next step) */
+    int32_t lattice;
+    int32_t storage;
+    int64_t bytes_per_update; /* algorithmic HBM bytes of one site update (pops r+w + table) */
+    int64_t device_bytes;     /* device memory held by the handle */
+} hemelb_lb_info_t;
+
+/*
+ * Neighbour table from a voxel label grid (host only, no device work).
+ * Implements the upstream classification of pull streaming (Section 2): for each
+ * fluid site x and direction i, the point x - c_i is a fluid site, a wall, or lies
+ * past an iolet.
+ *   labels    uint8 [(X+2)][(Y+2)][(Z+2)], point (x,y,z) at [x+1][y+1][z+1];
+ *             0 solid, 1 fluid (only inside the box), 2+k past iolet k
+ *   shape     {X, Y, Z}, each >= 1
+ *   periodic  {px, py, pz}: nonzero wraps that axis (its padding is unused)
+ *   lattice   15 or 19
+ *   n_sites   out: number of fluid sites N
+ *   coords    out (host, may be NULL): int32 [N][3], lexicographic order (x slowest)
+ *   nbr       out (host, may be NULL): int32 [N][lattice] upstream codes as above
+ * Call with coords = nbr = NULL to obtain N, then again with arrays of that size.
+ * Errors: EINVAL for bad shape/lattice or labels > 2+254; ENOMEM.
+ */
+int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t periodic[3],
+                    int32_t lattice, int64_t* n_sites, int32_t* coords, int32_t* nbr);
+
+/*
+ * Create a handle: validate (no device work on failure), Morton-order the sites,
+ * build the device neighbour table, allocate ping-pong population buffers and
+ * set the rest equilibrium at time 0.
+ * Errors: EINVAL (message names the first offending site/direction), ENOMEM, EDEVICE.
+ */
+int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* desc);
+
+/* Release all device memory of the handle (after finishing its queued work). */
+int hemelb_lb_destroy(hemelb_lb_t h);
+
+/*
+ * Enqueue n >= 0 time steps (Section 2: propagation + collision; Table 3 counts
+ * these as site updates) on the handle's stream and return without waiting.
+ * Each step launches an iolet ghost fill (if the geometry has iolets) and one
+ * fused stream+collide kernel.  Errors: EINVAL (n < 0), ECANCELLED, EDEVICE.
+ */
+int hemelb_lb_step(hemelb_lb_t h, int64_t n);
+
+/* Wait for the handle's queued work; reports EDIVERGED if a check failed. */
+int hemelb_lb_sync(hemelb_lb_t h);
+
+/* Run a divergence check (non-finite density or momentum) every `every` steps (0: off). */
+int hemelb_lb_set_check(hemelb_lb_t h, int64_t every);
+
+/* Ask a running hemelb_lb_step() on another thread to stop between steps. */
+int hemelb_lb_cancel(hemelb_lb_t h);
+
+/* Use another stream for subsequent work (hipStream_t, NULL = default). */
+int hemelb_lb_set_stream(hemelb_lb_t h, void* stream);
+
+/*
+ * Observables of the current time ("lattice properties computed and cached",
+ * Section 3.C.2), from the pre-collision populations of the last step (from the
+ * stored populations when no step has run since create/set_state):
+ *   p    float [N] device, pressure deviation (rho - 1) / 3 from the reference
+ *        density 1 (lattice units; p = rho/3 minus 1/3, kept as a deviation so
+ *        that FP32 does not round it away), or NULL
+ *   u    float [N][3] device, velocity, or NULL
+ *   wss  float [N] device, wall shear stress |sigma n - (n.sigma n) n| with
+ *        sigma = -(1 - 1/(2 tau)) sum_i c_i c_i (f_i - f_i^eq); 0 at sites without
+ *        a wall link, or NULL
+ * Caller site order.  Asynchronous on the handle's stream.
+ */
+int hemelb_lb_observables(hemelb_lb_t h, float* p, float* u, float* wss);
+
+/*
+ * Totals of the stored populations in FP64: out[0] = total mass sum_s rho_s,
+ * out[1..3] = total momentum.  host `out`; waits for the stream.
+ */
+int hemelb_lb_totals(hemelb_lb_t h, double out[4]);
+
+/*
+ * Stored populations in the storage format (checkpoint / resume):
+ *   dst/src  device, [lattice][N] in caller order; element type float (F32) or
+ *            16-bit (F16/BF16); value = (f_i - w_i) * scale_i, where scale_i is a
+ *            power of two (1 for F32 and with HEMELB_FLAG_NO_SCALE; see DESIGN).
+ *   t        out/in: completed steps.  set_state resets the "last step" of the
+ *            observables to the given state.
+ */
+int hemelb_lb_get_state(hemelb_lb_t h, void* dst, int64_t* t);
+int hemelb_lb_set_state(hemelb_lb_t h, const void* src, int64_t t);
+
+/* Decoded FP32 deviations f_i - w_i, device [lattice][N] in caller order. */
+int hemelb_lb_get_deviations(hemelb_lb_t h, float* dst);
+int hemelb_lb_set_deviations(hemelb_lb_t h, const float* src, int64_t t);
+
+/* Sizes, time and byte counts of a handle (host `info`). */
+int hemelb_lb_info(hemelb_lb_t h, hemelb_lb_info_t* info);
+
+/*
+ * Kernel timing with HIP events recorded on the handle's stream around every
+ * fused stream+collide launch of subsequent steps (capacity: max_launches; 0
+ * turns timing off).  hemelb_lb_kernel_time waits and returns the summed
+ * milliseconds and the number of timed launches (host pointers).
+ */
+int hemelb_lb_kernel_timing(hemelb_lb_t h, int64_t max_launches);
+int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches);
+
+/*
+ * Plain device copy of `bytes` (multiple of 16, 16-byte aligned device pointers)
+ * on `stream`: the practical bandwidth ceiling and a counter calibration for
+ * the stream+collide kernel.  Errors: EINVAL, EDEVICE.
+ */
+int hemelb_copy_probe(void* dst, const void* src, int64_t bytes, void* stream);
+
+/* Thread-local message of the last failure; static text for a code. */
+const char* hemelb_lb_last_error(void);
+const char* hemelb_lb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEMELB_LB_H */

@@ -1,0 +1,68 @@
+// Internal launch interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlb {
+
+constexpr int kBlock = 256;  // threads per block (4 wavefronts of 64)
+
+// Device copy of an iolet descriptor; harmonics live in a separate double array.
+struct DevIolet {
+    int32_t kind;      // 0 pressure, 1 velocity
+    int32_t n_harm;
+    int32_t harm_off;  // offset of cos (then sin) coefficients in the harmonic array
+    int32_t pad;
+    double mean;
+    double period;
+};
+
+// Layout of one handle's device data, shared by all launches.
+struct Layout {
+    int q;
+    int storage;
+    bool scaled;
+    int64_t n;       // fluid sites
+    int64_t pitch;   // elements between direction arrays of a population buffer
+    int64_t tpitch;  // elements between direction rows of the table
+    const int32_t* tbl;  // [(q-1)][tpitch] internal pull indices
+};
+
+struct Ghosts {
+    int64_t count;
+    const int32_t* site;   // Morton site index of each iolet link
+    const uint8_t* dir;    // direction of the link
+    const uint8_t* iolet;  // iolet id
+    const float* coef;     // 6 w_i (c_i . e_k) W_s for velocity links, else 0
+    const DevIolet* iolets;
+    const double* harm;
+};
+
+hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t t,
+                             hipStream_t s);
+
+hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, float omega,
+                                 const float* alpha, bool xcd_remap, hipStream_t s);
+
+// streamed != 0: gather pre-collision populations from `A` (the previous buffer,
+// ghosts included); 0: use the populations of `A` in place.
+hipError_t launch_observables(const Layout& L, const void* A, int streamed, float omega,
+                              const int32_t* perm, const float* normal, float* p, float* u,
+                              float* wss, hipStream_t s);
+
+// FP64 totals of the stored state into out[4]; sets *flag = 1 on a non-finite value.
+hipError_t launch_totals(const Layout& L, const void* A, double* partial, int64_t nparts,
+                         double* out, int32_t* flag, hipStream_t s);
+int64_t totals_parts(int64_t n);
+
+// mode 0: raw get, 1: raw set, 2: decoded get (float), 3: decoded set (float)
+hipError_t launch_state(const Layout& L, void* A, void* ext, const int32_t* perm, int mode,
+                        hipStream_t s);
+
+// fill every population of A (all directions, sites and ghosts) with deviation 0
+hipError_t launch_zero(const Layout& L, void* A, hipStream_t s);
+
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
+
+}  // namespace hlb

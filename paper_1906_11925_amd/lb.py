@@ -1,0 +1,222 @@
+"""Python front end of the C ABI: an `LB` handle over torch device memory.
+
+Argument marshalling only; the neighbour-table build runs in the library's
+C++ host code and every time step, observable and reduction in its HIP
+kernels.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import lib as L
+
+_STORE = {"f32": L.STORE_F32, "f16": L.STORE_F16, "bf16": L.STORE_BF16}
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(L.P(ctype)) if a is not None else None
+
+
+def links(labels, shape, periodic, lattice):
+    """(coords int32 [N,3], nbr int32 [N,Q]) from a padded label grid (C++ builder)."""
+    lib = L.load()
+    lab = np.ascontiguousarray(labels, dtype=np.uint8)
+    X, Y, Z = (int(v) for v in shape)
+    if lab.shape != (X + 2, Y + 2, Z + 2):
+        raise ValueError(f"labels must have shape {(X + 2, Y + 2, Z + 2)}, got {lab.shape}")
+    shp = np.array([X, Y, Z], dtype=np.int32)
+    per = np.array([1 if p else 0 for p in periodic], dtype=np.int32)
+    n = ctypes.c_int64(0)
+    L.check(lib.hemelb_lb_links(_ptr(lab, ctypes.c_uint8), _ptr(shp, L.c_int32), _ptr(per, L.c_int32),
+                                lattice, ctypes.byref(n), None, None))
+    coords = np.empty((n.value, 3), dtype=np.int32)
+    nbr = np.empty((n.value, lattice), dtype=np.int32)
+    L.check(lib.hemelb_lb_links(_ptr(lab, ctypes.c_uint8), _ptr(shp, L.c_int32), _ptr(per, L.c_int32),
+                                lattice, ctypes.byref(n), _ptr(coords, L.c_int32), _ptr(nbr, L.c_int32)))
+    return coords, nbr
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class LB:
+    """One simulation handle on the current GPU (see include/hemelb_lb.h)."""
+
+    def __init__(self, nbr, tau, lattice=15, storage="f32", coords=None, iolets=(),
+                 site_weight=None, wall_normal=None, alpha=None, stream=None, scale=True):
+        torch = _torch()
+        self.lib = L.load()
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        n = nbr.shape[0]
+        if nbr.ndim != 2 or nbr.shape[1] != lattice:
+            raise ValueError("nbr must be [N, lattice]")
+        self.n, self.q, self.storage = n, lattice, storage
+        self.tau = float(tau)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        keep = []
+        io_arr = (L.IoletT * max(1, len(iolets)))()
+        for k, io in enumerate(iolets):
+            cos = np.ascontiguousarray(getattr(io, "cos", ()), dtype=np.float64)
+            sin = np.ascontiguousarray(getattr(io, "sin", ()), dtype=np.float64)
+            if cos.shape != sin.shape:
+                raise ValueError("cos and sin harmonics must have the same length")
+            keep += [cos, sin]
+            io_arr[k].kind = L.IOLET_PRESSURE if io.kind == "pressure" else L.IOLET_VELOCITY
+            for a in range(3):
+                io_arr[k].direction[a] = float(io.direction[a])
+            io_arr[k].mean = float(io.mean)
+            io_arr[k].n_harm = int(cos.size)
+            io_arr[k].cos_k = _ptr(cos, L.c_double) if cos.size else None
+            io_arr[k].sin_k = _ptr(sin, L.c_double) if sin.size else None
+            io_arr[k].period = float(getattr(io, "period", 1.0))
+        d = L.DescT()
+        d.lattice = lattice
+        d.storage = _STORE[storage]
+        d.flags = 0 if scale else L.FLAG_NO_SCALE
+        d.n_sites = n
+        if coords is not None:
+            coords = np.ascontiguousarray(coords, dtype=np.int32)
+            keep.append(coords)
+            d.coords = _ptr(coords, L.c_int32)
+        d.nbr = _ptr(nbr, L.c_int32)
+        d.tau = self.tau
+        d.n_iolets = len(iolets)
+        d.iolets = io_arr
+        for name, arr, ct, dt in (("site_weight", site_weight, L.c_double, np.float64),
+                                  ("wall_normal", wall_normal, L.c_float, np.float32),
+                                  ("alpha", alpha, L.c_float, np.float32)):
+            if arr is not None:
+                a = np.ascontiguousarray(arr, dtype=dt)
+                keep.append(a)
+                setattr(d, name, _ptr(a, ct))
+        d.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = ctypes.c_void_p()
+        L.check(self.lib.hemelb_lb_create(ctypes.byref(h), ctypes.byref(d)))
+        self.h = h
+        del keep
+
+    @classmethod
+    def from_geometry(cls, geom, lattice=15, storage="f32", tau=None, alpha=None, **kw):
+        coords, nbr = links(geom.labels, geom.shape, geom.periodic, lattice)
+        return cls(nbr, geom.tau if tau is None else tau, lattice=lattice, storage=storage,
+                   coords=coords, iolets=list(geom.iolets), site_weight=geom.site_weight(),
+                   alpha=alpha, **kw)
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.check(self.lib.hemelb_lb_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping --------------------------------------------------------------
+    def step(self, n=1):
+        L.check(self.lib.hemelb_lb_step(self.h, int(n)))
+
+    def sync(self):
+        L.check(self.lib.hemelb_lb_sync(self.h))
+
+    def set_check(self, every):
+        L.check(self.lib.hemelb_lb_set_check(self.h, int(every)))
+
+    def cancel(self):
+        L.check(self.lib.hemelb_lb_cancel(self.h))
+
+    def info(self):
+        i = L.InfoT()
+        L.check(self.lib.hemelb_lb_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in L.InfoT._fields_}
+
+    @property
+    def time(self):
+        return self.info()["time"]
+
+    # -- outputs -----------------------------------------------------------------
+    def observables(self):
+        """(p_dev [N], u [N, 3], wss [N]) float32 CUDA tensors in caller order."""
+        torch = _torch()
+        p = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        u = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        w = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        L.check(self.lib.hemelb_lb_observables(self.h, ctypes.c_void_p(p.data_ptr()),
+                                               ctypes.c_void_p(u.data_ptr()),
+                                               ctypes.c_void_p(w.data_ptr())))
+        return p, u, w
+
+    def totals(self):
+        out = (ctypes.c_double * 4)()
+        L.check(self.lib.hemelb_lb_totals(self.h, out))
+        return np.array(list(out))
+
+    def _raw_dtype(self):
+        torch = _torch()
+        return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.storage]
+
+    def get_state(self):
+        torch = _torch()
+        dst = torch.empty((self.q, self.n), dtype=self._raw_dtype(), device="cuda")
+        t = ctypes.c_int64(0)
+        L.check(self.lib.hemelb_lb_get_state(self.h, ctypes.c_void_p(dst.data_ptr()), ctypes.byref(t)))
+        return dst, t.value
+
+    def set_state(self, src, t=0):
+        src = src.contiguous()
+        if src.dtype != self._raw_dtype() or tuple(src.shape) != (self.q, self.n):
+            raise ValueError("state must be [Q, N] in the storage dtype")
+        L.check(self.lib.hemelb_lb_set_state(self.h, ctypes.c_void_p(src.data_ptr()), int(t)))
+        self._keep = src
+
+    def get_deviations(self):
+        torch = _torch()
+        dst = torch.empty((self.q, self.n), dtype=torch.float32, device="cuda")
+        L.check(self.lib.hemelb_lb_get_deviations(self.h, ctypes.c_void_p(dst.data_ptr())))
+        return dst
+
+    def set_deviations(self, src, t=0):
+        torch = _torch()
+        src = src.to(device="cuda", dtype=torch.float32).contiguous()
+        if tuple(src.shape) != (self.q, self.n):
+            raise ValueError("deviations must be [Q, N]")
+        L.check(self.lib.hemelb_lb_set_deviations(self.h, ctypes.c_void_p(src.data_ptr()), int(t)))
+        self._keep = src
+
+    # -- timing -------------------------------------------------------------------
+    def kernel_timing(self, max_launches):
+        L.check(self.lib.hemelb_lb_kernel_timing(self.h, int(max_launches)))
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0)
+        k = ctypes.c_int64(0)
+        L.check(self.lib.hemelb_lb_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+
+def copy_probe(dst, src, nbytes, stream=None):
+    """Plain device copy kernel (bandwidth ceiling / counter calibration)."""
+    torch = _torch()
+    lib = L.load()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    L.check(lib.hemelb_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  int(nbytes), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def relaxation_time(viscosity, step, voxel, density=1000.0):
+    """tau = 1/2 + 3 nu dt / dx^2 for a physical dynamic viscosity (Pa s), time
+    step (s), voxel size (m) and density (kg/m^3); Table 1 and Section 4 give
+    dt = 2e-5 s, dx = 1e-4 m, mu = 0.004 Pa s."""
+    nu = viscosity / density
+    return 0.5 + 3.0 * nu * step / (voxel * voxel)
+
+
+__all__ = ["LB", "links", "copy_probe", "relaxation_time"]

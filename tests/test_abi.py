@@ -1,0 +1,131 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects
+invalid arguments on the host before any device work (CPU-only)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from paper_1906_11925_amd import lib as L
+from paper_1906_11925_amd import links
+
+
+def test_exports_every_declared_symbol():
+    lib = L.load()
+    names = L.header_functions()
+    assert "hemelb_lb_create" in names and "hemelb_lb_step" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L._SIGS), "binding signatures out of sync with the header"
+
+
+def test_strerror():
+    lib = L.load()
+    assert lib.hemelb_lb_strerror(L.HEMELB_EINVAL) == b"invalid argument"
+    assert lib.hemelb_lb_strerror(0) == b"success"
+
+
+def _desc(nbr, q=15, tau=0.8, storage=0, flags=0, iolets=None, n_iolets=0, coords=None,
+          alpha=None):
+    d = L.DescT()
+    d.lattice, d.storage, d.flags = q, storage, flags
+    d.n_sites = nbr.shape[0]
+    d.nbr = nbr.ctypes.data_as(L.P(L.c_int32))
+    d.tau = tau
+    d.n_iolets = n_iolets
+    d.iolets = iolets
+    if coords is not None:
+        d.coords = coords.ctypes.data_as(L.P(L.c_int32))
+    if alpha is not None:
+        d.alpha = alpha.ctypes.data_as(L.P(L.c_float))
+    return d
+
+
+def _create(d):
+    lib = L.load()
+    h = ctypes.c_void_p()
+    rc = lib.hemelb_lb_create(ctypes.byref(h), ctypes.byref(d))
+    return rc, L.last_error()
+
+
+@pytest.fixture(scope="module")
+def box():
+    g = wl.closed_box(4, 3, 5)
+    coords, nbr = links(g.labels, g.shape, g.periodic, 15)
+    return coords, nbr
+
+
+def test_reject_bad_lattice(box):
+    _, nbr = box
+    rc, msg = _create(_desc(nbr, q=17))
+    assert rc == L.HEMELB_EINVAL and "lattice" in msg
+
+
+@pytest.mark.parametrize("tau", [0.5, 0.3, float("nan")])
+def test_reject_bad_tau(box, tau):
+    _, nbr = box
+    rc, msg = _create(_desc(nbr, tau=tau))
+    assert rc == L.HEMELB_EINVAL and "tau" in msg
+
+
+def test_reject_bad_storage_and_flags(box):
+    _, nbr = box
+    assert _create(_desc(nbr, storage=7))[0] == L.HEMELB_EINVAL
+    assert _create(_desc(nbr, flags=8))[0] == L.HEMELB_EINVAL
+
+
+def test_reject_nonreciprocal_link(box):
+    _, nbr = box
+    bad = nbr.copy()
+    s = 3
+    i = next(i for i in range(1, 15) if bad[s, i] >= 0)
+    bad[s, i] = (bad[s, i] + 1) % bad.shape[0]
+    rc, msg = _create(_desc(bad))
+    assert rc == L.HEMELB_EINVAL and "reciprocal" in msg and f"({s}, {i})" in msg
+
+
+def test_reject_out_of_range_and_unknown_iolet(box):
+    _, nbr = box
+    bad = nbr.copy()
+    bad[0, 1] = bad.shape[0] + 5
+    assert _create(_desc(bad))[0] == L.HEMELB_EINVAL
+    bad = nbr.copy()
+    bad[0, 1] = -2  # iolet 0, but no iolets given
+    rc, msg = _create(_desc(bad))
+    assert rc == L.HEMELB_EINVAL and "iolet" in msg
+
+
+def test_reject_bad_iolet_descriptor(box):
+    _, nbr = box
+    io = (L.IoletT * 1)()
+    io[0].kind = 5
+    rc, msg = _create(_desc(nbr, iolets=io, n_iolets=1))
+    assert rc == L.HEMELB_EINVAL and "kind" in msg
+    io[0].kind = L.IOLET_VELOCITY
+    io[0].n_harm = 2  # harmonics without arrays
+    rc, msg = _create(_desc(nbr, iolets=io, n_iolets=1))
+    assert rc == L.HEMELB_EINVAL and "harmonics" in msg
+
+
+def test_reject_bad_coords_and_alpha(box):
+    coords, nbr = box
+    c = coords.copy()
+    c[2, 1] = -1
+    assert _create(_desc(nbr, coords=c))[0] == L.HEMELB_EINVAL
+    c = coords.copy()
+    c[1] = c[0]
+    rc, msg = _create(_desc(nbr, coords=c))
+    assert rc == L.HEMELB_EINVAL and "duplicate" in msg
+    a = np.full(nbr.shape[0], 0.5, dtype=np.float32)
+    a[4] = 1.5
+    rc, msg = _create(_desc(nbr, alpha=a))
+    assert rc == L.HEMELB_EINVAL and "alpha" in msg
+
+
+def test_null_handle_calls():
+    lib = L.load()
+    assert lib.hemelb_lb_step(None, 1) == L.HEMELB_EINVAL
+    assert lib.hemelb_lb_destroy(None) == L.HEMELB_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lib.hemelb_lb_totals(None, out) == L.HEMELB_EINVAL

@@ -1,0 +1,366 @@
+"""GPU path (HIP kernels through the C ABI) against the FP64 oracle.
+
+Bit-exact pins: the rest equilibrium stays exactly zero deviation; with the
+collision switched off (tau = infinity) a step is a pure permutation of the
+stored values, identical to the oracle's streaming; results do not depend on
+the site order given to the library; checkpoint/restore is exact.
+
+Toleranced pins (FP32 arithmetic vs FP64): one step from a random state,
+element by element; multi-step runs compared on the observables with the
+error metric max_s |x_gpu - x_ref| / max_s |x_ref| (velocity as a vector, and
+pressure deviation and wall shear stress likewise): FP32 storage <= 1e-5,
+FP16 storage <= 2e-3 after the run.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as wl  # noqa: E402
+from workloads.geometry import Geometry, Iolet  # noqa: E402
+from oracle.lbgk import LBGK  # noqa: E402
+from oracle import lattice as olat  # noqa: E402
+from paper_1906_11925_amd import LB, HemelbError  # noqa: E402
+from paper_1906_11925_amd import lib as L  # noqa: E402
+
+from lbtest import quantize, rel_max, rel_l2, SCALES  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dev(lb):
+    return lb.get_deviations().cpu().numpy().astype(np.float64)
+
+
+def _walls_only(g):
+    lab = g.labels.copy()
+    lab[lab >= 2] = 0
+    return Geometry(g.name + "_walls", g.shape, lab, periodic=g.periodic, iolets=[], tau=g.tau)
+
+
+def _still(g):
+    ios = [Iolet(io.kind, direction=io.direction, mean=(1.0 if io.kind == "pressure" else 0.0))
+           for io in g.iolets]
+    return Geometry(g.name + "_still", g.shape, g.labels, periodic=g.periodic, iolets=ios,
+                    tau=g.tau, profile=g.profile)
+
+
+STORAGES = ["f32", "f16", "bf16"]
+
+
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("storage", STORAGES)
+def test_rest_state_stays_exact(storage, q):
+    _gpu()
+    for g in (_still(wl.pipe()), _still(wl.aneurysm(half=True)), wl.couette(U=0.0)):
+        lb = LB.from_geometry(g, lattice=q, storage=storage)
+        lb.step(7)
+        raw, t = lb.get_state()
+        assert t == 7
+        assert torch.count_nonzero(raw.float()) == 0
+        p, u, w = lb.observables()
+        assert torch.count_nonzero(p) == 0 and torch.count_nonzero(u) == 0
+        assert torch.count_nonzero(w) == 0
+        lb.close()
+
+
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("name", ["closed", "periodic", "pipe_walls", "tree_walls"])
+def test_no_collision_is_exact_permutation(name, storage, q):
+    """tau = infinity: each step only moves stored values; identical to the
+    oracle's pull streaming applied to the same values."""
+    _gpu()
+    g = {"closed": lambda: wl.closed_box(7, 6, 5), "periodic": lambda: wl.periodic_box(5, 7, 6),
+         "pipe_walls": lambda: _walls_only(wl.pipe()),
+         "tree_walls": lambda: _walls_only(
+             wl.tree(box=96, r0=6.0, root=(48.0, 48.0, 4.0), generations=3, seed=1))}[name]()
+    o = LBGK(g, q, tau=math.inf)
+    d = quantize(wl.random_deviations(q, o.n, 21, 1e-2), q, storage)
+    lb = LB.from_geometry(g, lattice=q, storage=storage, tau=math.inf)
+    lb.set_deviations(torch.from_numpy(d))
+    ref = d
+    for t in range(3):
+        ref = o.stream(ref, t)
+    lb.step(3)
+    assert np.array_equal(_dev(lb), ref)
+    lb.close()
+
+
+def fp32_tol(q, amp):
+    """Bound on the FP32 error of one step from deviations of size <= amp.
+
+    Summing q terms of size <= amp in FP32 errs by at most (q-1) u sum|d_i|
+    <= q^2 amp u (u = 2^-24); the equilibrium and collision reuse these sums
+    with O(1) factors, hence 2 q^2 amp u for deviations, velocity and stress
+    (and a third of it for the pressure deviation drho/3).  A wrong term, sign
+    or weight shows up at the size of w_i * amp ~ 1e-5..1e-4, far above this.
+    """
+    return 2.0 * q * q * amp * 2.0 ** -24
+
+
+def _one_step_case(g, q, storage, seed, amp=1e-3, tau=None, alpha=None):
+    o = LBGK(g, q, tau=tau, alpha=alpha)
+    d = quantize(wl.random_deviations(q, o.n, seed, amp), q, storage)
+    t0 = 37
+    lb = LB.from_geometry(g, lattice=q, storage=storage, tau=tau,
+                          alpha=None if alpha is None else alpha.astype(np.float32))
+    lb.set_deviations(torch.from_numpy(d), t=t0)
+    lb.step(1)
+    gpu = _dev(lb)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    A, f = o.step(o.lat.w[:, None] + d, t0)
+    ref = A - o.lat.w[:, None]
+    op, ou, _, ow = o.observables(f)
+    lb.close()
+    return gpu, ref, (p, u, w), (op - 1.0 / 3.0, ou.T, ow), o
+
+
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("name", ["pipe", "aneurysm_half", "couette", "channel", "tree_small"])
+def test_one_step_f32_elementwise(name, q):
+    _gpu()
+    g = {"pipe": wl.pipe, "aneurysm_half": lambda: wl.aneurysm(half=True),
+         "couette": wl.couette, "channel": wl.channel,
+         "tree_small": lambda: wl.tree(box=96, r0=6.0, root=(48.0, 48.0, 4.0), generations=3,
+                                       seed=1)}[name]()
+    gpu, ref, (p, u, w), (op, ou, ow), _ = _one_step_case(g, q, "f32", seed=5)
+    tol = fp32_tol(q, 1e-3)
+    assert np.abs(gpu - ref).max() < tol
+    assert np.abs(p - op).max() < tol / 3
+    assert np.abs(u - ou).max() < tol
+    assert np.abs(w - ow).max() < tol
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_one_step_16bit_elementwise(storage):
+    _gpu()
+    q = 15
+    gpu, ref, _, _, _ = _one_step_case(wl.aneurysm(half=True), q, storage, seed=6)
+    ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
+    s = SCALES[q][:, None]
+    # input exact; one FP32 collision then one rounding of d * scale
+    tol = ulp * np.abs(ref) + fp32_tol(q, 1e-3) + (2.0 ** -24 / s if storage == "f16" else 0.0)
+    assert np.all(np.abs(gpu - ref) <= tol)
+
+
+def test_one_step_brinkman_alpha():
+    _gpu()
+    g = wl.aneurysm(half=True)
+    n = g.n_sites
+    alpha = np.random.default_rng(4).uniform(0.0, 0.01, n)
+    alpha = alpha.astype(np.float32).astype(np.float64)
+    gpu, ref, _, _, _ = _one_step_case(g, 15, "f32", seed=8, alpha=alpha)
+    assert np.abs(gpu - ref).max() < fp32_tol(15, 1e-3)
+
+
+def test_site_order_invariance_bit_exact():
+    """Morton-ordered and caller-ordered runs give identical bits."""
+    _gpu()
+    g = wl.aneurysm(half=True)
+    from paper_1906_11925_amd import links
+    coords, nbr = links(g.labels, g.shape, g.periodic, 15)
+    a = LB(nbr, g.tau, coords=coords, iolets=g.iolets, site_weight=g.site_weight())
+    b = LB(nbr, g.tau, coords=None, iolets=g.iolets, site_weight=g.site_weight())
+    d = torch.from_numpy(quantize(wl.random_deviations(15, g.n_sites, 3, 1e-3), 15, "f32"))
+    for lb in (a, b):
+        lb.set_deviations(d)
+        lb.step(20)
+    sa, sb = a.get_state()[0], b.get_state()[0]
+    assert torch.equal(sa, sb)
+    for x, y in zip(a.observables(), b.observables()):
+        assert torch.equal(x, y)
+
+
+def test_checkpoint_restart_bit_exact():
+    _gpu()
+    g = wl.aneurysm(half=True)
+    a = LB.from_geometry(g, storage="f16")
+    a.step(40)
+    b = LB.from_geometry(g, storage="f16")
+    b.step(20)
+    st, t = b.get_state()
+    c = LB.from_geometry(g, storage="f16")
+    c.set_state(st.clone(), t)
+    c.step(20)
+    assert c.time == 40
+    assert torch.equal(a.get_state()[0], c.get_state()[0])
+
+
+def test_determinism():
+    _gpu()
+    g = wl.pipe()
+    runs = []
+    for _ in range(2):
+        lb = LB.from_geometry(g)
+        lb.step(50)
+        runs.append((lb.get_state()[0], lb.totals()))
+    assert torch.equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.fixture(scope="module")
+def pipe_oracle():
+    g = wl.pipe()
+    o = LBGK(g, 15)
+    A, f = o.run(o.rest_state(), 0, 2000)
+    p, u, _, w = o.observables(f)
+    return g, A, (p - 1.0 / 3.0, u.T, w)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 2e-3)])
+def test_pipe_2000_steps_vs_oracle(pipe_oracle, storage, tol):
+    """Straight pipe, D3Q15, tau = 0.8, pressure iolets, 2000 steps from rest."""
+    _gpu()
+    g, A, (op, ou, ow) = pipe_oracle
+    lb = LB.from_geometry(g, storage=storage)
+    lb.step(2000)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    eu, ep, ew = rel_max(u, ou), rel_max(p, op), rel_max(w, ow)
+    print(f"pipe {storage}: e_u={eu:.3e} e_p={ep:.3e} e_wss={ew:.3e} "
+          f"l2_u={rel_l2(u, ou):.3e}", flush=True)
+    assert eu <= tol and ep <= tol and ew <= tol
+
+
+def test_pipe_bf16_error_reported(pipe_oracle):
+    _gpu()
+    g, A, (op, ou, ow) = pipe_oracle
+    lb = LB.from_geometry(g, storage="bf16")
+    lb.step(2000)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    eu = rel_max(u, ou)
+    print(f"pipe bf16: e_u={eu:.3e} e_p={rel_max(p, op):.3e} e_wss={rel_max(w, ow):.3e}", flush=True)
+    assert eu < 5e-2
+
+
+def test_aneurysm_half_pulsatile_vs_oracle():
+    """Half-size aneurysm with the pulsatile Ladd inlet, 200 steps from rest."""
+    _gpu()
+    g = wl.aneurysm(half=True)
+    o = LBGK(g, 15)
+    A, f = o.run(o.rest_state(), 0, 200)
+    op, ou, _, ow = o.observables(f)
+    lb = LB.from_geometry(g)
+    lb.step(200)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    eu, ep, ew = rel_max(u, ou.T), rel_max(p, op - 1 / 3), rel_max(w, ow)
+    print(f"aneurysm_half f32: e_u={eu:.3e} e_p={ep:.3e} e_wss={ew:.3e}", flush=True)
+    assert eu <= 1e-5 and ep <= 1e-5 and ew <= 1e-5
+
+
+def test_pipe_d3q19_vs_oracle():
+    _gpu()
+    g = wl.pipe()
+    o = LBGK(g, 19)
+    A, f = o.run(o.rest_state(), 0, 500)
+    op, ou, _, ow = o.observables(f)
+    lb = LB.from_geometry(g, lattice=19)
+    lb.step(500)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    assert rel_max(u, ou.T) <= 1e-5 and rel_max(p, op - 1 / 3) <= 1e-5 and rel_max(w, ow) <= 1e-5
+
+
+def test_couette_wss_closed_form():
+    _gpu()
+    H, U, tau = 8, 0.01, 1.0
+    g = wl.couette(H=H, Lx=2, Lz=2, U=U, tau=tau)
+    lb = LB.from_geometry(g)
+    lb.step(1200)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    y = g.coords[:, 1]
+    nu = (tau - 0.5) / 3
+    assert np.abs(u[:, 0] - U * (y + 0.5) / H).max() / U < 1e-5
+    np.testing.assert_allclose(w[y == 0], nu * U / H, rtol=1e-4)
+
+
+def test_observables_at_time_zero_use_stored_state():
+    _gpu()
+    g = wl.pipe()
+    o = LBGK(g, 15)
+    d = quantize(wl.random_deviations(15, o.n, 9, 1e-3), 15, "f32")
+    lb = LB.from_geometry(g)
+    lb.set_deviations(torch.from_numpy(d), t=5)
+    p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+    op, ou, _, ow = o.observables(o.lat.w[:, None] + d)
+    assert np.abs(p - (op - 1 / 3)).max() < 1e-9
+    assert np.abs(u - ou.T).max() < 1e-8
+
+
+def test_totals_and_mass_conservation():
+    _gpu()
+    g = wl.closed_box(9, 8, 7)
+    o = LBGK(g, 15, tau=0.55)
+    d = quantize(wl.random_deviations(15, o.n, 12, 5e-4), 15, "f32")
+    lb = LB.from_geometry(g, tau=0.55)
+    lb.set_deviations(torch.from_numpy(d))
+    t0 = lb.totals()
+    m, mom = o.totals(o.lat.w[:, None] + d)
+    assert abs(t0[0] - m) < 1e-9 and np.abs(t0[1:] - mom).max() < 1e-12
+    lb.step(1000)
+    t1 = lb.totals()
+    print(f"closed box FP32 mass drift over 1000 steps: {(t1[0] - t0[0]) / t0[0]:.3e}", flush=True)
+    assert abs(t1[0] - t0[0]) / t0[0] < 1e-6
+
+
+def test_divergence_check_reports_nonfinite():
+    _gpu()
+    g = wl.closed_box(5, 5, 5)
+    lb = LB.from_geometry(g)
+    d = np.zeros((15, g.n_sites))
+    d[3, 10] = np.nan
+    lb.set_deviations(torch.from_numpy(d))
+    lb.set_check(2)
+    lb.step(4)
+    with pytest.raises(HemelbError) as ei:
+        lb.sync()
+    assert ei.value.code == L.HEMELB_EDIVERGED
+
+
+def test_empty_geometry():
+    _gpu()
+    lb = LB(np.zeros((0, 15), dtype=np.int32), 0.7)
+    lb.step(3)
+    p, u, w = lb.observables()
+    assert p.numel() == 0
+    assert lb.totals()[0] == 0.0
+    lb.close()
+
+
+def test_cancel_stops_step_request():
+    _gpu()
+    lb = LB.from_geometry(wl.closed_box(4, 4, 4))
+    lb.cancel()
+    with pytest.raises(HemelbError) as ei:
+        lb.step(5)
+    assert ei.value.code == L.HEMELB_ECANCELLED
+    lb.step(2)
+    assert lb.time == 2
+
+
+def test_kernel_timing_counts_launches():
+    _gpu()
+    lb = LB.from_geometry(wl.pipe())
+    lb.kernel_timing(10)
+    lb.step(10)
+    ms, k = lb.kernel_time()
+    assert k == 10 and ms > 0
+
+
+@pytest.mark.parametrize("name", ["aneurysm", "tree1024"])
+def test_full_size_one_step(name):
+    """Full-size workloads, launched as the benchmark launches them: one step
+    from a random state compared element by element with the oracle."""
+    _gpu()
+    g = wl.config_geometry(name)
+    gpu, ref, (p, u, w), (op, ou, ow), o = _one_step_case(g, 15, "f32", seed=13)
+    print(f"{name}: {o.n} sites", flush=True)
+    assert np.abs(gpu - ref).max() < fp32_tol(15, 1e-3)
+    assert np.abs(u - ou).max() < fp32_tol(15, 1e-3)
