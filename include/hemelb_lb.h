@@ -137,7 +137,7 @@ typedef struct {
 typedef struct {
     int64_t n_sites;     /* N */
     int64_t n_ghosts;    /* iolet links (one ghost population each) */
-    int64_t pitch;       /* elements between direction arrays of a population buffer */
+    int64_t pitch;       /* slots per direction (sites + ghost links, whole 64-site tiles) */
     int64_t time;        /* completed steps (boundary time of the next step) */
     int32_t lattice;
     int32_t storage;

@@ -115,7 +115,7 @@ void parallel_for(int64_t n, F&& f) {
 struct hemelb_lb {
     int q = 15, storage = 0, flags = 0;
     bool scaled = false;
-    int64_t n = 0, nghost = 0, pitch = 0, tpitch = 0;
+    int64_t n = 0, nghost = 0, slots = 0, ttiles = 0;
     double tau = 0;
     float omega = 0;
     hipStream_t stream = nullptr;
@@ -150,7 +150,7 @@ struct hemelb_lb {
     int64_t device_bytes = 0;
 
     hlb::Layout layout() const {
-        return hlb::Layout{q, storage, scaled, n, pitch, tpitch, tbl};
+        return hlb::Layout{q, storage, scaled, n, slots, tbl};
     }
     hlb::Ghosts ghosts() const {
         return hlb::Ghosts{nghost, g_site, g_dir, g_iolet, g_coef, d_iolets, d_harm};
@@ -485,15 +485,15 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         delete h;
         return fail(HEMELB_EINVAL, "sites + iolet links must stay below 2^30");
     }
-    h->pitch = ((n + h->nghost + 255) / 256) * 256;
-    if (h->pitch == 0) h->pitch = 256;
-    h->tpitch = ((n + 63) / 64) * 64;
-    if (h->tpitch == 0) h->tpitch = 64;
+    h->slots = ((n + h->nghost + hlb::kTile - 1) / hlb::kTile) * hlb::kTile;
+    if (h->slots == 0) h->slots = hlb::kTile;
+    h->ttiles = (n + hlb::kTile - 1) / hlb::kTile;
+    if (h->ttiles == 0) h->ttiles = 1;
 
-    // internal pull table [(q-1)][tpitch]: fluid -> Morton index of the upstream
-    // site; wall -> own index offset by one direction array (so that reading
-    // direction i at that index yields opp(i) of the same site); iolet -> ghost slot
-    std::vector<int32_t> tbl((size_t)(q - 1) * h->tpitch, 0);
+    // internal pull table [tile][q-1][64]: fluid -> Morton index of the upstream
+    // site; wall -> own index with bit 31 set (read the opposite direction of the
+    // same site); iolet -> ghost slot n + l
+    std::vector<int32_t> tbl((size_t)h->ttiles * (q - 1) * hlb::kTile, 0);
     {
         std::vector<int64_t> gbase(n + 1, 0);
         for (int64_t l = 0; l < h->nghost; ++l) gbase[gsite[l] + 1]++;
@@ -503,14 +503,16 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
             int64_t g = gbase[m];
             for (int i = 1; i < q; ++i) {
                 const int32_t v = d->nbr[s * q + i];
-                int64_t e;
+                uint32_t e;
                 if (v >= 0)
-                    e = inv[v];
+                    e = (uint32_t)inv[v];
                 else if (v == HEMELB_LINK_WALL)
-                    e = m + (int64_t)(opp_dir(i) - i) * h->pitch;
+                    e = (uint32_t)m | 0x80000000u;
                 else
-                    e = n + (g++);
-                tbl[(size_t)(i - 1) * h->tpitch + m] = (int32_t)e;
+                    e = (uint32_t)(n + (g++));
+                const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
+                                  (size_t)(m % hlb::kTile);
+                tbl[at] = (int32_t)e;
             }
         }
     }
@@ -563,7 +565,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
             return _r;      \
         }                   \
     } while (0)
-    const size_t popbytes = (size_t)q * h->pitch * h->elem();
+    const size_t popbytes = (size_t)q * h->slots * h->elem();
     for (int b = 0; b < 2; ++b) {
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, popbytes);
@@ -716,7 +718,7 @@ int hemelb_lb_info(hemelb_lb_t h, hemelb_lb_info_t* info) {
     if (!h || !info) return fail(HEMELB_EINVAL, "NULL argument");
     info->n_sites = h->n;
     info->n_ghosts = h->nghost;
-    info->pitch = h->pitch;
+    info->pitch = h->slots;
     info->time = h->t;
     info->lattice = h->q;
     info->storage = h->storage;

@@ -2,15 +2,19 @@
 //
 // The time step (paper Section 2: propagation and collision on a sparse lattice
 // of fluid sites) is one fused kernel per step: every thread owns one fluid site,
-// pulls its populations through the int32 neighbour table (wall links point at
-// the opposite population of the same site, iolet links at a ghost slot filled
-// just before by the ghost-fill kernel), applies the LBGK collision in FP32 and
-// writes the post-collision populations with coalesced stores.  The work is a
-// gather/scatter stencil at ~1.3 flop per byte, bound by HBM bandwidth, so there
-// is no matrix-core work and no LDS staging: the kernel is written for wide
-// memory-level parallelism (all table and population loads of a thread issued
-// before any arithmetic) and for L2 locality (Morton-ordered sites, blocks
-// mapped to XCDs in contiguous ranges).
+// pulls its populations through the int32 neighbour table (a wall link names the
+// site itself with the top bit set and reads its opposite population; an iolet
+// link names a ghost slot filled just before by the ghost-fill kernel), applies
+// the LBGK collision in FP32 and stores the post-collision populations.  The work
+// is a gather/scatter stencil at ~1.3 flop per byte, bound by HBM bandwidth, so
+// there is no matrix-core work and no LDS staging.
+//
+// Memory layout: sites are Morton-ordered and grouped in tiles of 64, the width of
+// a wavefront.  Populations are stored [tile][direction][64] and the table
+// [tile][direction-1][64], so one wavefront's stores of all directions and its
+// table loads each cover one contiguous block (3.75 KB and 3.5 KB for D3Q15 in
+// FP32) instead of 2Q separate address streams; every per-direction access of a
+// wavefront is a 256-byte (FP32) or 128-byte (16-bit) aligned chunk.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,6 +42,19 @@ static hipError_t dispatch(int q, int st, bool scaled, F&& f) {
         if (st == ST_BF16) return scaled ? f(Tag<19, ST_BF16, true>{}) : f(Tag<19, ST_BF16, false>{});
     }
     return hipErrorInvalidValue;
+}
+
+// element (direction i, site s) of a tiled array with R rows per tile
+template <int R>
+__device__ inline int64_t tix(int i, int32_t s) {
+    return ((int64_t)(s >> kTileShift) * R + i) * kTile + (s & (kTile - 1));
+}
+
+// decode a table entry for direction i: (source direction, source site)
+__device__ inline void link_src(int i, int32_t j, int& dir, int32_t& site) {
+    const bool wall = j < 0;
+    dir = wall ? opp(i) : i;
+    site = j & 0x7fffffff;
 }
 
 // moments of FP32 deviations: drho = sum d, m = sum c d (constant-folded per lattice)
@@ -79,26 +96,66 @@ __device__ inline void eq_dev(float drho, float rho, float ux, float uy, float u
 // ---------------------------------------------------------------------------
 // fused pull stream + LBGK collide
 // ---------------------------------------------------------------------------
+// Build-time tuning knobs (every variant computes the same result):
+//   HLB_NT_STORE  nontemporal stores of the post-collision populations
+//   HLB_NT_TABLE  nontemporal loads of the neighbour table
+//   HLB_SC_BLOCK  threads per block of this kernel (a multiple of 64)
+#ifndef HLB_NT_STORE
+#define HLB_NT_STORE 1
+#endif
+#ifndef HLB_NT_TABLE
+#define HLB_NT_TABLE 1
+#endif
+#ifndef HLB_SC_BLOCK
+#define HLB_SC_BLOCK 256
+#endif
+constexpr int kScBlock = HLB_SC_BLOCK;
+static_assert(kScBlock % kTile == 0, "block must hold whole tiles");
+
+template <class T>
+__device__ inline T ld_table(const T* p) {
+#if HLB_NT_TABLE
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class T>
+__device__ inline void st_pop(T* p, T v) {
+#if HLB_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <int Q, int ST, bool SC, bool BRINK>
-__global__ __launch_bounds__(kBlock) void k_stream_collide(
+__global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    const int32_t* __restrict__ tbl, int32_t n, int64_t pitch, int64_t tpitch, int32_t per_xcd,
-    float omega, const float* __restrict__ alpha) {
+    const int32_t* __restrict__ tbl, int32_t n, int32_t per_xcd, float omega,
+    const float* __restrict__ alpha) {
     using C = Codec<Q, ST, SC>;
     // consecutive block ids are dealt round-robin to the 8 XCDs; give each XCD a
     // contiguous range of sites so that neighbour gathers hit its own L2
     int32_t b = blockIdx.x;
     if (per_xcd > 0) b = (b & 7) * per_xcd + (b >> 3);
-    const int32_t s = b * kBlock + (int32_t)threadIdx.x;
+    const int32_t s = b * kScBlock + (int32_t)threadIdx.x;
     if (s >= n) return;
 
+    // all table loads, then all population gathers, before any arithmetic
     int32_t j[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) j[i] = tbl[(int64_t)(i - 1) * tpitch + s];
+    for (int i = 1; i < Q; ++i) j[i] = ld_table(tbl + tix<Q - 1>(i - 1, s));
     float d[Q];
-    d[0] = C::dec(0, src[s]);
+    d[0] = C::dec(0, src[tix<Q>(0, s)]);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) d[i] = C::dec(i, src[(int64_t)i * pitch + j[i]]);
+    for (int i = 1; i < Q; ++i) {
+        int dir;
+        int32_t site;
+        link_src(i, j[i], dir, site);
+        d[i] = C::dec(i, src[tix<Q>(dir, site)]);
+    }
 
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -116,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float v = d[i] - omega * (d[i] - deq[i]);
-        dst[(int64_t)i * pitch + s] = C::enc(i, v);
+        st_pop(dst + tix<Q>(i, s), C::enc(i, v));
     }
 }
 
@@ -136,8 +193,7 @@ __device__ inline double iolet_value(const DevIolet& io, const double* harm, dou
 
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __restrict__ A,
-                                                        Ghosts G, int32_t n, int64_t pitch,
-                                                        double t) {
+                                                        Ghosts G, int32_t n, double t) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -151,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __
         // equilibrium at the iolet density with the site's own (lagged) velocity
         float d[Q];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) d[k] = C::dec(k, A[(int64_t)k * pitch + s]);
+        for (int k = 0; k < Q; ++k) d[k] = C::dec(k, A[tix<Q>(k, s)]);
         float drho, mx, my, mz;
         moments<Q>(d, drho, mx, my, mz);
         const float ir = 1.0f / (1.0f + drho);
@@ -163,9 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __
     } else {
         // Ladd moving-wall bounce-back
         const int o = opp(i);
-        g = C::dec(o, A[(int64_t)o * pitch + s]) + G.coef[l] * (float)v;
+        g = C::dec(o, A[tix<Q>(o, s)]) + G.coef[l] * (float)v;
     }
-    A[(int64_t)i * pitch + n + l] = C::enc(i, g);
+    A[tix<Q>(i, n + (int32_t)l)] = C::enc(i, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_observables(
     const typename Store<ST>::T* __restrict__ A, const int32_t* __restrict__ tbl, int32_t n,
-    int64_t pitch, int64_t tpitch, int32_t streamed, float omega, const int32_t* __restrict__ perm,
+    int32_t streamed, float omega, const int32_t* __restrict__ perm,
     const float* __restrict__ normal, float* __restrict__ p, float* __restrict__ u,
     float* __restrict__ wss) {
     using C = Codec<Q, ST, SC>;
@@ -182,11 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_observables(
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
     float d[Q];
-    d[0] = C::dec(0, A[s]);
+    d[0] = C::dec(0, A[tix<Q>(0, s)]);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int32_t j = streamed ? tbl[(int64_t)(i - 1) * tpitch + s] : s;
-        d[i] = C::dec(i, A[(int64_t)i * pitch + j]);
+        int dir = i;
+        int32_t site = s;
+        if (streamed) link_src(i, tbl[tix<Q - 1>(i - 1, s)], dir, site);
+        d[i] = C::dec(i, A[tix<Q>(dir, site)]);
     }
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -247,8 +305,7 @@ __device__ inline double wave_sum(double v) {
 
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_totals(const typename Store<ST>::T* __restrict__ A,
-                                                    int32_t n, int64_t pitch,
-                                                    double* __restrict__ partial,
+                                                    int32_t n, double* __restrict__ partial,
                                                     int32_t* __restrict__ flag) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
@@ -259,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_totals(const typename Store<ST>::T* 
         double r = 0, x = 0, y = 0, z = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = C::dec(i, A[(int64_t)i * pitch + s]);
+            const double v = C::dec(i, A[tix<Q>(i, (int32_t)s)]);
             r += v;
             x += Lt::cx[i] * v;
             y += Lt::cy[i] * v;
@@ -308,20 +365,20 @@ __global__ __launch_bounds__(kBlock) void k_totals_final(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// state transfer between the internal (Morton, pitched) and caller layouts
+// state transfer between the internal (Morton, tiled) and caller layouts
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_state(typename Store<ST>::T* __restrict__ A,
                                                    void* __restrict__ ext,
                                                    const int32_t* __restrict__ perm, int32_t n,
-                                                   int64_t pitch, int mode) {
+                                                   int mode) {
     using C = Codec<Q, ST, SC>;
     using T = typename Store<ST>::T;
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     const int i = blockIdx.y;
     if (s >= n) return;
     const int64_t e = (int64_t)i * n + (perm ? perm[s] : s);
-    const int64_t a = (int64_t)i * pitch + s;
+    const int64_t a = tix<Q>(i, s);
     switch (mode) {
         case 0: static_cast<T*>(ext)[e] = A[a]; break;
         case 1: A[a] = static_cast<const T*>(ext)[e]; break;
@@ -357,7 +414,7 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_ghost_fill<Tg::Q, Tg::ST, Tg::SC><<<blocks_for(G.count), kBlock, 0, s>>>(
-            static_cast<T*>(A), G, (int32_t)L.n, L.pitch, (double)t);
+            static_cast<T*>(A), G, (int32_t)L.n, (double)t);
         return hipGetLastError();
     });
 }
@@ -365,7 +422,7 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
 hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, float omega,
                                  const float* alpha, bool xcd_remap, hipStream_t s) {
     if (L.n == 0) return hipSuccess;
-    const int64_t nb = (L.n + kBlock - 1) / kBlock;
+    const int64_t nb = (L.n + kScBlock - 1) / kScBlock;
     int32_t per = 0;
     int64_t grid = nb;
     if (xcd_remap) {
@@ -376,13 +433,13 @@ hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, fl
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         if (alpha)
-            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true><<<(unsigned)grid, kBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, L.pitch,
-                L.tpitch, per, omega, alpha);
+            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true><<<(unsigned)grid, kScBlock, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, per, omega,
+                alpha);
         else
-            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false><<<(unsigned)grid, kBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, L.pitch,
-                L.tpitch, per, omega, nullptr);
+            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false><<<(unsigned)grid, kScBlock, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, per, omega,
+                nullptr);
         return hipGetLastError();
     });
 }
@@ -395,8 +452,8 @@ hipError_t launch_observables(const Layout& L, const void* A, int streamed, floa
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_observables<Tg::Q, Tg::ST, Tg::SC><<<blocks_for(L.n), kBlock, 0, s>>>(
-            static_cast<const T*>(A), L.tbl, (int32_t)L.n, L.pitch, L.tpitch, streamed, omega,
-            perm, normal, p, u, wss);
+            static_cast<const T*>(A), L.tbl, (int32_t)L.n, streamed, omega, perm, normal, p, u,
+            wss);
         return hipGetLastError();
     });
 }
@@ -407,7 +464,7 @@ hipError_t launch_totals(const Layout& L, const void* A, double* partial, int64_
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_totals<Tg::Q, Tg::ST, Tg::SC><<<(unsigned)nparts, kBlock, 0, s>>>(
-            static_cast<const T*>(A), (int32_t)L.n, L.pitch, partial, flag);
+            static_cast<const T*>(A), (int32_t)L.n, partial, flag);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
@@ -423,13 +480,13 @@ hipError_t launch_state(const Layout& L, void* A, void* ext, const int32_t* perm
         using T = typename Store<Tg::ST>::T;
         dim3 grid(blocks_for(L.n), (unsigned)Tg::Q);
         k_state<Tg::Q, Tg::ST, Tg::SC><<<grid, kBlock, 0, s>>>(static_cast<T*>(A), ext, perm,
-                                                                (int32_t)L.n, L.pitch, mode);
+                                                                (int32_t)L.n, mode);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_zero(const Layout& L, void* A, hipStream_t s) {
-    const int64_t bytes = (int64_t)L.q * L.pitch * (int64_t)elem_size(L.storage);
+    const int64_t bytes = (int64_t)L.q * L.slots * (int64_t)elem_size(L.storage);
     const int64_t words = bytes / 4;
     int64_t nb = (words + kBlock - 1) / kBlock;
     if (nb > 4096) nb = 4096;

@@ -7,6 +7,8 @@
 namespace hlb {
 
 constexpr int kBlock = 256;  // threads per block (4 wavefronts of 64)
+constexpr int kTile = 64;    // sites per tile of the [tile][direction][64] layouts
+constexpr int kTileShift = 6;
 
 // Device copy of an iolet descriptor; harmonics live in a separate double array.
 struct DevIolet {
@@ -18,15 +20,17 @@ struct DevIolet {
     double period;
 };
 
-// Layout of one handle's device data, shared by all launches.
+// Layout of one handle's device data, shared by all launches.  Populations are
+// stored [slots/64][q][64] (sites, then ghost slots, Morton order), the table
+// [ceil(n/64)][q-1][64]; a table entry is the source site (>= 0), the site
+// itself with bit 31 set for a bounce-back wall link, or n + l for ghost l.
 struct Layout {
     int q;
     int storage;
     bool scaled;
-    int64_t n;       // fluid sites
-    int64_t pitch;   // elements between direction arrays of a population buffer
-    int64_t tpitch;  // elements between direction rows of the table
-    const int32_t* tbl;  // [(q-1)][tpitch] internal pull indices
+    int64_t n;      // fluid sites
+    int64_t slots;  // site + ghost slots per direction, a multiple of 64
+    const int32_t* tbl;
 };
 
 struct Ghosts {

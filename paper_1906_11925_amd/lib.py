@@ -11,7 +11,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhemelb_lb.so")
+LIB_PATH = os.environ.get("HEMELB_LIB") or os.path.join(HERE, "libhemelb_lb.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hemelb_lb.h")
 
 c_int32, c_int64, c_double, c_float, c_void_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,

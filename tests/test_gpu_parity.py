@@ -142,14 +142,33 @@ def test_one_step_f32_elementwise(name, q):
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_one_step_16bit_elementwise(storage):
+    """16-bit storage: the input is exact, one FP32 collision follows, then one
+    rounding of d * scale (relative half-ulp 2^-11 for FP16, 2^-8 for BF16).
+    Incoming populations at iolet links are stored in the same format, so
+    their rounding (bounded with the oracle's ghost values) also enters the
+    collision of their site, with a Jacobian of norm below 3."""
     _gpu()
     q = 15
-    gpu, ref, _, _, _ = _one_step_case(wl.aneurysm(half=True), q, storage, seed=6)
+    g = wl.aneurysm(half=True)
+    o = LBGK(g, q)
+    d = quantize(wl.random_deviations(q, o.n, 6, 1e-3), q, storage)
+    lb = LB.from_geometry(g, lattice=q, storage=storage)
+    lb.set_deviations(torch.from_numpy(d), t=37)
+    lb.step(1)
+    gpu = _dev(lb)
+    lb.close()
+    A, f = o.step(o.lat.w[:, None] + d, 37)
+    ref = A - o.lat.w[:, None]
     ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
     s = SCALES[q][:, None]
-    # input exact; one FP32 collision then one rounding of d * scale
-    tol = ulp * np.abs(ref) + fp32_tol(q, 1e-3) + (2.0 ** -24 / s if storage == "f16" else 0.0)
+    sub = 2.0 ** -25 / s if storage == "f16" else 0.0 * s
+    ghost = o.links.kind == 2
+    g_err = np.where(ghost, ulp * np.abs(f - o.lat.w[:, None]) + sub, 0.0).sum(axis=0)
+    tol = ulp * np.abs(ref) + sub + fp32_tol(q, 1e-3) + 3.0 * g_err[None, :]
     assert np.all(np.abs(gpu - ref) <= tol)
+    # away from iolets the bound is the plain rounding bound
+    plain = ~ghost.any(axis=0)
+    assert np.all(np.abs(gpu - ref)[:, plain] <= (ulp * np.abs(ref) + sub + fp32_tol(q, 1e-3))[:, plain])
 
 
 def test_one_step_brinkman_alpha():
