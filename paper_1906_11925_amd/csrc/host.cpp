@@ -140,7 +140,7 @@ struct hemelb_lb {
 
     int64_t t = 0;
     bool streamed = false;
-    bool xcd_remap = true;
+    int xcd_group = 16;  // consecutive 256-site blocks per XCD (measured best at 8-16)
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
 
@@ -269,7 +269,7 @@ int do_step(hemelb_lb* h) {
     HIP_TRY(hlb::launch_ghost_fill(L, h->ghosts(), src, h->t, h->stream), "ghost fill");
     const bool timed = h->ev_used + 2 <= (int64_t)h->ev.size() && h->ev_cap > 0;
     if (timed) HIP_TRY(hipEventRecord(h->ev[h->ev_used], h->stream), "event");
-    HIP_TRY(hlb::launch_stream_collide(L, src, dst, h->omega, h->alpha, h->xcd_remap, h->stream),
+    HIP_TRY(hlb::launch_stream_collide(L, src, dst, h->omega, h->alpha, h->xcd_group, h->stream),
             "stream collide");
     if (timed) {
         HIP_TRY(hipEventRecord(h->ev[h->ev_used + 1], h->stream), "event");
@@ -422,7 +422,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     h->tau = d->tau;
     h->omega = std::isinf(d->tau) ? 0.0f : (float)(1.0 / d->tau);
     h->stream = static_cast<hipStream_t>(d->stream);
-    if (const char* e = getenv("HEMELB_XCD_REMAP")) h->xcd_remap = atoi(e) != 0;
+    if (const char* e = getenv("HEMELB_XCD_GROUP")) h->xcd_group = std::max(0, atoi(e));
     (void)hipGetDevice(&h->device);
     const int q = h->q;
     const int64_t n = h->n;

@@ -133,13 +133,18 @@ __device__ inline void st_pop(T* p, T v) {
 template <int Q, int ST, bool SC, bool BRINK>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    const int32_t* __restrict__ tbl, int32_t n, int32_t per_xcd, float omega,
+    const int32_t* __restrict__ tbl, int32_t n, int32_t xcd_group, float omega,
     const float* __restrict__ alpha) {
     using C = Codec<Q, ST, SC>;
-    // consecutive block ids are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of sites so that neighbour gathers hit its own L2
+    // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
+    // xcd_group = G > 0, every XCD takes G consecutive tiles-blocks of a window of
+    // 8G blocks, so neighbouring sites share an L2 while all XCDs still sweep the
+    // Morton order together (and share the last-level cache).
     int32_t b = blockIdx.x;
-    if (per_xcd > 0) b = (b & 7) * per_xcd + (b >> 3);
+    if (xcd_group > 0) {
+        const int32_t w = 8 * xcd_group;
+        b = (b / w) * w + (b & 7) * xcd_group + (b >> 3) % xcd_group;
+    }
     const int32_t s = b * kScBlock + (int32_t)threadIdx.x;
     if (s >= n) return;
 
@@ -420,15 +425,12 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
 }
 
 hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, float omega,
-                                 const float* alpha, bool xcd_remap, hipStream_t s) {
+                                 const float* alpha, int xcd_group, hipStream_t s) {
     if (L.n == 0) return hipSuccess;
     const int64_t nb = (L.n + kScBlock - 1) / kScBlock;
-    int32_t per = 0;
+    const int32_t per = xcd_group > 0 ? xcd_group : 0;
     int64_t grid = nb;
-    if (xcd_remap) {
-        per = (int32_t)((nb + 7) / 8);
-        grid = (int64_t)per * 8;
-    }
+    if (per > 0) grid = ((nb + 8 * per - 1) / (8 * per)) * (8 * per);
     return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;

@@ -46,8 +46,9 @@ struct Ghosts {
 hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t t,
                              hipStream_t s);
 
+// xcd_group: consecutive blocks per XCD in the block-to-tile mapping (0: identity)
 hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, float omega,
-                                 const float* alpha, bool xcd_remap, hipStream_t s);
+                                 const float* alpha, int xcd_group, hipStream_t s);
 
 // streamed != 0: gather pre-collision populations from `A` (the previous buffer,
 // ghosts included); 0: use the populations of `A` in place.
