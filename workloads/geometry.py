@@ -132,12 +132,14 @@ def _in_box(shape, x, y, z):
 # straight pipe with pressure iolets
 # ----------------------------------------------------------------------------
 
-def pipe(X=20, Y=20, Z=64, r2=64.0, rho_in=1.001, rho_out=1.0, tau=0.8):
+def pipe(X=20, Y=20, Z=64, r2=64.0, rho_in=1.001, rho_out=1.0, tau=0.8, inlet_velocity=None):
     """Straight circular pipe along z: fluid iff (x-cx)^2+(y-cy)^2 < r2, 0<=z<Z.
 
     Iolet 0 (inlet) lies beyond z = 0, iolet 1 (outlet) beyond z = Z-1, both
     pressure (equilibrium) iolets.  The default is the 20x20x64 pipe with
-    radius 8 and 208 sites per cross-section (13,312 sites).
+    radius 8 and 208 sites per cross-section (13,312 sites).  With
+    ``inlet_velocity=(mean, cos, sin, period)`` the inlet is instead a Ladd
+    velocity iolet along +z with a parabolic profile.
     """
     shape = (X, Y, Z)
     lab = _empty(shape)
@@ -149,7 +151,13 @@ def pipe(X=20, Y=20, Z=64, r2=64.0, rho_in=1.001, rho_out=1.0, tau=0.8):
     lab[(disc & (z < 0))] = 2
     lab[(disc & (z >= Z))] = 3
     iolets = [Iolet("pressure", mean=rho_in), Iolet("pressure", mean=rho_out)]
-    return Geometry("pipe", shape, lab, iolets=iolets, tau=tau,
+    profile = None
+    if inlet_velocity is not None:
+        mean, cos, sin, period = inlet_velocity
+        iolets[0] = Iolet("velocity", direction=(0.0, 0.0, 1.0), mean=mean, cos=tuple(cos),
+                          sin=tuple(sin), period=period)
+        profile = ((cx, cy, 0.0), (0.0, 0.0, 1.0), float(np.sqrt(r2)))
+    return Geometry("pipe", shape, lab, iolets=iolets, tau=tau, profile=profile,
                     info=dict(r2=r2, rho_in=rho_in, rho_out=rho_out))
 
 
