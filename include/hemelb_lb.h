@@ -250,6 +250,85 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches);
  */
 int hemelb_copy_probe(void* dst, const void* src, int64_t bytes, void* stream);
 
+/*
+ * Differentiation of the time step.  The paper's step (Section 2) is the map
+ * A_t -> A_{t+1} defined at the top of this header; these calls run its exact
+ * discrete adjoint (reverse mode, FP32 adjoint populations, FP64 accumulation of
+ * parameter gradients) for the objective
+ *   J = sum_{t0<=t<t1} (Q(t) - q_target)^2 + lam * mean_t mean_{s in D} WSS_s(t),
+ * where Q(t) = sum over the links (s, i) of iolet `outlet` of A_t[opp(i)][s] - f_i(s)
+ * is the mass leaving through that iolet during step t and WSS is the wall
+ * shear stress of hemelb_lb_observables (Section 3.C.2's lattice properties)
+ * at the dome sites D (sites with a wall normal among those marked in `dome`).
+ * Parameters: the Fourier coefficients of every velocity iolet and the per-site
+ * Brinkman field alpha.
+ *   outlet    iolet id
+ *   q_target  Q*
+ *   dome      host uint8 [N] caller order (nonzero: in D), or NULL (no shear term)
+ *   lam       weight of the shear term
+ *   t0, t1    window of steps, 0 <= t0 <= t1
+ */
+typedef struct {
+    int32_t outlet;
+    double q_target;
+    const uint8_t* dome;
+    double lam;
+    int64_t t0, t1;
+} hemelb_objective_t;
+
+/*
+ * Replace the time series of iolet k (inlet velocity waveform, Section 3.B /
+ * Figure 6).  kind, n_harm and direction must equal those given at create.
+ * Waits for the handle's stream.  Errors: EINVAL.
+ */
+int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io);
+
+/* Replace the Brinkman field: host float [N] in [0, 1], caller order, or NULL for none. */
+int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha);
+
+/*
+ * Set (or clear, obj = NULL) the objective.  Subsequent steps inside the window
+ * record Q(t) and the dome shear on the device.  Clearing or replacing it ends
+ * any adjoint run.  Errors: EINVAL.
+ */
+int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj);
+
+/*
+ * J and its two terms (host doubles, any may be NULL), after the forward run has
+ * passed the window end; hemelb_lb_objective_flux copies Q(t) for the window's
+ * t1 - t0 steps to host `q`.  Waits.  Errors: EORDER.
+ */
+int hemelb_lb_objective_value(hemelb_lb_t h, double* J, double* flux_term, double* wss_term);
+int hemelb_lb_objective_flux(hemelb_lb_t h, double* q);
+
+/*
+ * Start the reverse sweep at the handle's current time T (the end of the forward
+ * run): dJ/dA_T = 0, gradients zero.  max_segment bounds the steps of one
+ * recompute segment (the tape holds max_segment + 1 population buffers).
+ * Errors: EORDER (no objective), EINVAL, ENOMEM.
+ */
+int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment);
+
+/*
+ * One checkpoint segment, processed backwards: restore `checkpoint` (device,
+ * raw state of hemelb_lb_get_state taken at time t0), recompute steps
+ * t0 .. t0+steps-1 onto the tape, then run their adjoint steps in reverse.
+ * Segments must be called in reverse order so that t0 + steps equals the time
+ * reached by the previous segment (T for the first).  Asynchronous.
+ * Errors: EORDER, EINVAL.
+ */
+int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps);
+
+/*
+ * Gradients accumulated so far (waits).  dtheta: host doubles, for every velocity
+ * iolet in id order its 1 + 2 n_harm derivatives (mean, cos_1..n, sin_1..n);
+ * dalpha: host doubles [N] caller order.  Either may be NULL.  Errors: EORDER.
+ */
+int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha);
+
+/* Current adjoint populations dJ/dA_t (device float [lattice][N], caller order). */
+int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst);
+
 /* Thread-local message of the last failure; static text for a code. */
 const char* hemelb_lb_last_error(void);
 const char* hemelb_lb_strerror(int code);

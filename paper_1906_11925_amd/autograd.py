@@ -1,0 +1,59 @@
+"""torch.autograd.Function over N time steps with checkpoint/recompute.
+
+Forward: from the rest state, run N steps of the library's forward kernels,
+keeping the raw population state every K steps (device tensors) while the
+library records the objective's terms; return J (FP64).  Backward: for each
+K-step segment in reverse, the library restores the segment's checkpoint,
+recomputes it onto a K+1-buffer tape and runs the hand-written adjoint
+kernels backwards through it; the FP64 gradients with respect to the velocity
+inlet's Fourier coefficients and the Brinkman field come back scaled by the
+incoming gradient of J.  Memory: ceil(N/K) checkpoints plus K+1 tape buffers.
+"""
+
+import dataclasses
+
+import numpy as np
+import torch
+
+
+def _with_coefficients(io, theta):
+    H = len(getattr(io, "cos", ()))
+    th = [float(x) for x in theta]
+    return dataclasses.replace(io, mean=th[0], cos=tuple(th[1:1 + H]), sin=tuple(th[1 + H:]))
+
+
+class LBAdjointFn(torch.autograd.Function):
+    """J = LBAdjointFn.apply(theta, alpha, lb, inlet, steps, K).
+
+    theta: FP64 tensor [1 + 2H], the (mean, cos_1..H, sin_1..H) coefficients of
+    velocity iolet `inlet`; alpha: tensor [N] (caller site order), the Brinkman
+    field; lb: an `LB` handle with an objective set (`LB.set_objective`).
+    """
+
+    @staticmethod
+    def forward(ctx, theta, alpha, lb, inlet, steps, K):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        lb.set_iolet(inlet, _with_coefficients(lb.iolets[inlet], th))
+        lb.set_alpha(alpha.detach().to("cpu", torch.float32).numpy())
+        lb.set_deviations(torch.zeros((lb.q, lb.n), dtype=torch.float32, device="cuda"), t=0)
+        checkpoints = []
+        for t0 in range(0, steps, K):
+            checkpoints.append((t0, min(K, steps - t0), lb.get_state()[0].clone()))
+            lb.step(min(K, steps - t0))
+        J, _, _ = lb.objective_value()
+        ctx.lb, ctx.inlet, ctx.K, ctx.checkpoints = lb, inlet, K, checkpoints
+        ctx.alpha_meta = (alpha.dtype, alpha.device)
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        lb = ctx.lb
+        lb.adjoint_begin(ctx.K)
+        for t0, k, ck in reversed(ctx.checkpoints):
+            lb.adjoint_segment(ck, t0, k)
+        dth, da = lb.adjoint_grads()
+        g = float(gJ)
+        dtheta = torch.from_numpy(dth[ctx.inlet] * g)
+        dalpha = torch.from_numpy(np.asarray(da) * g).to(dtype=ctx.alpha_meta[0],
+                                                          device=ctx.alpha_meta[1])
+        return dtheta, dalpha, None, None, None, None

@@ -1,0 +1,346 @@
+// Discrete adjoint of the sparse LBGK step, and the objective it differentiates.
+//
+// Objective (over a window W of steps; step t maps A_t to A_{t+1} through the
+// pre-collision populations f_t):
+//   J = sum_{t in W} (Q(t) - Q*)^2 + lam * mean_{t in W} mean_{s in D} WSS_s(f_t),
+//   Q(t) = sum over the outlet's iolet links (s, i) of A_t[opp(i)][s] - f_t[i][s].
+//
+// One reverse step t (given g = dJ/dA_{t+1}, FP32, same tiled layout as the
+// populations) is two kernels:
+//  * k_adj_scatter, one thread per site: re-gathers f_t from the taped A_t,
+//    applies the transposed collision Jacobian
+//      fhat_j = (1 - omega) g_j + omega (a + c_j . b),
+//      a = sum_i g_i dfeq_i/drho, b = sum_i g_i dfeq_i/dm  (Brinkman-aware),
+//    adds the wall-shear objective term, accumulates dJ/dalpha_s in FP64, and
+//    writes fhat_i to exactly the address the forward pull read f_i from (the
+//    upstream site, the site's own opposite population for a wall link, or the
+//    link's ghost slot).  Every population location is read by at most one link,
+//    so the push needs no atomics; the populations that leave through iolets are
+//    read by nobody and are set to zero here.
+//  * k_adj_iolet, one thread per site with iolet links: turns the adjoints that
+//    landed in ghost slots into their sources: the Ladd term sends its adjoint to
+//    the site's opposite population and (times its coefficient and the Fourier
+//    basis) to the inlet coefficients; the pressure equilibrium sends it to all
+//    of the site's own populations through u(A_t[:, s]); the outlet flux term of
+//    the objective enters here too.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adjoint.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "lbdev.hpp"
+
+namespace hlb {
+
+constexpr int kObjBlock = 1024;
+
+// pre-collision populations (deviations) of site s from a state with filled ghosts
+template <int Q, int ST, bool SC>
+__device__ inline void gather_pre(const typename Store<ST>::T* __restrict__ A,
+                                  const int32_t* __restrict__ tbl, int32_t s, float (&d)[Q],
+                                  int32_t (&j)[Q]) {
+    using C = Codec<Q, ST, SC>;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) j[i] = tbl[tix<Q - 1>(i - 1, s)];
+    j[0] = s;
+    d[0] = C::dec(0, A[tix<Q>(0, s)]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        int dir;
+        int32_t site;
+        link_src(i, j[i], dir, site);
+        d[i] = C::dec(i, A[tix<Q>(dir, site)]);
+    }
+}
+
+// traction tangential to the wall, t = sigma n - (n.sigma n) n, with
+// sigma = -(1 - omega/2) sum_i c_i c_i (f_i - f_i^eq(rho, u))
+template <int Q>
+__device__ inline void shear(const float (&d)[Q], float drho, float ux, float uy, float uz,
+                             float omega, float nx, float ny, float nz, float& tx, float& ty,
+                             float& tz) {
+    using Lt = Lat<Q>;
+    float deq[Q];
+    eq_dev<Q>(drho, 1.0f + drho, ux, uy, uz, deq);
+    float pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const float e = d[i] - deq[i];
+        const float cx = Lt::cx[i], cy = Lt::cy[i], cz = Lt::cz[i];
+        if (Lt::cx[i]) pxx += e;
+        if (Lt::cy[i]) pyy += e;
+        if (Lt::cz[i]) pzz += e;
+        if (Lt::cx[i] && Lt::cy[i]) pxy += cx * cy * e;
+        if (Lt::cx[i] && Lt::cz[i]) pxz += cx * cz * e;
+        if (Lt::cy[i] && Lt::cz[i]) pyz += cy * cz * e;
+    }
+    const float k = -(1.0f - 0.5f * omega);
+    const float sx = k * (pxx * nx + pxy * ny + pxz * nz);
+    const float sy = k * (pxy * nx + pyy * ny + pyz * nz);
+    const float sz = k * (pxz * nx + pyz * ny + pzz * nz);
+    const float nsn = sx * nx + sy * ny + sz * nz;
+    tx = sx - nsn * nx;
+    ty = sy - nsn * ny;
+    tz = sz - nsn * nz;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// forward objective terms of one step: Q(t) and sum over D of WSS(f_t)
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool SC>
+__global__ __launch_bounds__(kObjBlock) void k_objective(
+    const typename Store<ST>::T* __restrict__ A, const int32_t* __restrict__ tbl, int32_t n,
+    Ghosts G, const int32_t* __restrict__ out_links, int32_t n_out,
+    const int32_t* __restrict__ dome, int32_t n_dome, const float* __restrict__ normal,
+    float omega, double* __restrict__ q_out, double* __restrict__ w_out) {
+    using C = Codec<Q, ST, SC>;
+    __shared__ double red[kObjBlock / 64];
+    double q = 0.0, w = 0.0;
+    for (int32_t k = threadIdx.x; k < n_out; k += kObjBlock) {
+        const int32_t l = out_links[k];
+        const int32_t s = G.site[l];
+        const int i = G.dir[l];
+        const int o = opp(i);
+        q += (double)C::dec(o, A[tix<Q>(o, s)]) - (double)C::dec(i, A[tix<Q>(i, n + l)]);
+    }
+    for (int32_t k = threadIdx.x; k < n_dome; k += kObjBlock) {
+        const int32_t s = dome[k];
+        float d[Q];
+        int32_t j[Q];
+        gather_pre<Q, ST, SC>(A, tbl, s, d, j);
+        float drho, mx, my, mz;
+        moments<Q>(d, drho, mx, my, mz);
+        const float ir = 1.0f / (1.0f + drho);
+        float tx, ty, tz;
+        shear<Q>(d, drho, mx * ir, my * ir, mz * ir, omega, normal[s], normal[n + s],
+                 normal[2 * (int64_t)n + s], tx, ty, tz);
+        w += sqrtf(tx * tx + ty * ty + tz * tz);
+    }
+    const double qs = block_sum(q, red);
+    const double ws = block_sum(w, red);
+    if (threadIdx.x == 0) {
+        *q_out = qs;
+        *w_out = ws;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse step: transposed collision + push along the forward's pull addresses
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool SC, bool BRINK>
+__global__ __launch_bounds__(kBlock) void k_adj_scatter(
+    const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
+    float* __restrict__ gout, const int32_t* __restrict__ tbl, int32_t n, float omega,
+    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
+    const float* __restrict__ wss_w, const float* __restrict__ normal) {
+    using Lt = Lat<Q>;
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    float d[Q];
+    int32_t j[Q];
+    gather_pre<Q, ST, SC>(A, tbl, s, d, j);
+    float g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = gin[tix<Q>(i, s)];
+
+    float drho, mx, my, mz;
+    moments<Q>(d, drho, mx, my, mz);
+    const float rho = 1.0f + drho;
+    const float ir = 1.0f / rho;
+    const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+    const float keep = BRINK ? 1.0f - alpha[s] : 1.0f;
+    const float bx = keep * ux, by = keep * uy, bz = keep * uz;
+    const float ub2 = bx * bx + by * by + bz * bz;
+    const float ubu = bx * ux + by * uy + bz * uz;
+    // a = sum g_i dfeq_i/drho,  b = sum g_i dfeq_i/dm,  alpha term
+    float a = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, ga = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float cx = Lt::cx[i], cy = Lt::cy[i], cz = Lt::cz[i];
+        const float cub = cx * bx + cy * by + cz * bz;
+        const float cu = cx * ux + cy * uy + cz * uz;
+        const float wg = Lt::w[i] * g[i];
+        a += wg * (1.0f - 4.5f * cub * cub + 1.5f * ub2);
+        const float t = wg * (3.0f + 9.0f * cub);
+        b0 += t * cx - 3.0f * wg * bx;
+        b1 += t * cy - 3.0f * wg * by;
+        b2 += t * cz - 3.0f * wg * bz;
+        if constexpr (BRINK) ga += wg * (3.0f * cu + 9.0f * cub * cu - 3.0f * ubu);
+    }
+    b0 *= keep;
+    b1 *= keep;
+    b2 *= keep;
+    if constexpr (BRINK) alpha_hat[s] += (double)(-omega * rho * ga);
+
+    float fh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        fh[i] = (1.0f - omega) * g[i] +
+                omega * (a + (float)Lt::cx[i] * b0 + (float)Lt::cy[i] * b1 + (float)Lt::cz[i] * b2);
+
+    // wall-shear objective: dWSS/df_j = -(1 - omega/2) (t^.(c_j - u)) (n.(c_j - u))
+    if (wss_w) {
+        const float ws = wss_w[s];
+        if (ws != 0.f) {
+            const float nx = normal[s], ny = normal[n + s], nz = normal[2 * (int64_t)n + s];
+            float tx, ty, tz;
+            shear<Q>(d, drho, ux, uy, uz, omega, nx, ny, nz, tx, ty, tz);
+            const float tn = sqrtf(tx * tx + ty * ty + tz * tz);
+            if (tn > 0.f) {
+                const float it = 1.0f / tn;
+                tx *= it;
+                ty *= it;
+                tz *= it;
+                const float kk = -(1.0f - 0.5f * omega) * ws;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const float ex = Lt::cx[i] - ux, ey = Lt::cy[i] - uy, ez = Lt::cz[i] - uz;
+                    fh[i] += kk * (tx * ex + ty * ey + tz * ez) * (nx * ex + ny * ey + nz * ez);
+                }
+            }
+        }
+    }
+
+    // push each adjoint to where the forward pulled the value from
+    gout[tix<Q>(0, s)] = fh[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        int dir;
+        int32_t site;
+        link_src(i, j[i], dir, site);
+        gout[tix<Q>(dir, site)] = fh[i];
+        // an iolet link: the population opp(i) of this site leaves the domain
+        if (j[i] >= n) gout[tix<Q>(opp(i), s)] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse step at iolet sites
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool SC>
+__global__ __launch_bounds__(kBlock) void k_adj_iolet(
+    const typename Store<ST>::T* __restrict__ A, float* __restrict__ gout, Ghosts G,
+    IoletSites S, int32_t n, double t, int32_t outlet, const double* __restrict__ q_tape,
+    int64_t q_index, double q_target, double* __restrict__ theta_acc, int32_t nbasis) {
+    using C = Codec<Q, ST, SC>;
+    using Lt = Lat<Q>;
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= S.count) return;
+    const int32_t s = S.site[k];
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(i, A[tix<Q>(i, s)]);
+    float drho, mx, my, mz;
+    moments<Q>(d, drho, mx, my, mz);
+    const float rA = 1.0f + drho;
+    const float ir = 1.0f / rA;
+    const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+    const double qbar = q_index >= 0 ? 2.0 * (q_tape[q_index] - q_target) : 0.0;
+    float acc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] = 0.f;
+    for (int32_t l = S.lo[k]; l < S.hi[k]; ++l) {
+        const int i = G.dir[l];
+        const int o = opp(i);
+        const int kio = G.iolet[l];
+        const DevIolet io = G.iolets[kio];
+        float gh = gout[tix<Q>(i, n + l)];
+        if (kio == outlet && q_index >= 0) {
+            gh -= (float)qbar;
+            acc[o] += (float)qbar;
+        }
+        if (io.kind == 1) {
+            acc[o] += gh;
+            // d value / d(mean, cos_h, sin_h)
+            const double c = (double)gh * (double)G.coef[l];
+            double* th = theta_acc + (int64_t)l * nbasis;
+            th[0] += c;
+            for (int h = 1; h <= io.n_harm; ++h) {
+                const double ph = fmod((double)h * t, io.period) / io.period;
+                double sv, cv;
+                sincospi(2.0 * ph, &sv, &cv);
+                th[h] += c * cv;
+                th[io.n_harm + h] += c * sv;
+            }
+        } else {
+            const float rk = (float)iolet_value(io, G.harm, t);
+            const float cix = Lt::cx[i], ciy = Lt::cy[i], ciz = Lt::cz[i];
+            const float cu = cix * ux + ciy * uy + ciz * uz;
+            const float sc = Lt::w[i] * rk;
+            const float gx = sc * (3.0f * cix + 9.0f * cu * cix - 3.0f * ux);
+            const float gy = sc * (3.0f * ciy + 9.0f * cu * ciy - 3.0f * uy);
+            const float gz = sc * (3.0f * ciz + 9.0f * cu * ciz - 3.0f * uz);
+            const float gi = gh * ir;
+#pragma unroll
+            for (int jd = 0; jd < Q; ++jd)
+                acc[jd] += gi * ((Lt::cx[jd] - ux) * gx + (Lt::cy[jd] - uy) * gy + (Lt::cz[jd] - uz) * gz);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        if (acc[i] != 0.f) gout[tix<Q>(i, s)] += acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, const Objective& O,
+                            const float* normal, float omega, double* q_out, double* w_out,
+                            hipStream_t s) {
+    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        k_objective<Tg::Q, Tg::ST, Tg::SC><<<1, kObjBlock, 0, s>>>(
+            static_cast<const T*>(A), L.tbl, (int32_t)L.n, G, O.out_links, O.n_out, O.dome,
+            O.n_dome, normal, omega, q_out, w_out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletSites& S, const void* A,
+                           const float* gin, float* gout, float omega, const float* alpha,
+                           double* alpha_hat, const float* wss_w, const float* normal, int64_t t,
+                           int32_t outlet, const double* q_tape, int64_t q_index,
+                           double q_target, double* theta_acc, int32_t nbasis, hipStream_t s) {
+    if (L.n == 0) return hipSuccess;
+    hipError_t e = dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        if (alpha)
+            k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, true><<<blocks(L.n), kBlock, 0, s>>>(
+                static_cast<const T*>(A), gin, gout, L.tbl, (int32_t)L.n, omega, alpha, alpha_hat,
+                wss_w, normal);
+        else
+            k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, false><<<blocks(L.n), kBlock, 0, s>>>(
+                static_cast<const T*>(A), gin, gout, L.tbl, (int32_t)L.n, omega, nullptr,
+                alpha_hat, wss_w, normal);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess || S.count == 0) return e;
+    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        k_adj_iolet<Tg::Q, Tg::ST, Tg::SC><<<blocks(S.count), kBlock, 0, s>>>(
+            static_cast<const T*>(A), gout, G, S, (int32_t)L.n, (double)t, outlet, q_tape, q_index,
+            q_target, theta_acc, nbasis);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace hlb

@@ -1,0 +1,43 @@
+// Internal launch interface of the objective and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace hlb {
+
+// device lists of the objective: the outlet's ghost links and the dome sites
+struct Objective {
+    const int32_t* out_links;  // ghost-link indices belonging to the outlet iolet
+    int32_t n_out;
+    const int32_t* dome;       // Morton indices of dome sites with a wall normal
+    int32_t n_dome;
+};
+
+// sites that own iolet links, with their (contiguous) ghost-link ranges
+struct IoletSites {
+    int64_t count;
+    const int32_t* site;
+    const int32_t* lo;
+    const int32_t* hi;
+};
+
+// Q(t) and the sum of WSS over the dome for the step whose pre-collision state
+// (ghosts filled) is A; single-block deterministic reduction.
+hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, const Objective& O,
+                            const float* normal, float omega, double* q_out, double* w_out,
+                            hipStream_t s);
+
+// One reverse step t: gin = dJ/dA_{t+1} -> gout = dJ/dA_t (FP32, tiled), accumulating
+// dJ/dalpha (FP64 per site) and the inlet-coefficient adjoints (FP64 per link).
+// wss_w: per-site weight of the wall-shear term, or null outside the window;
+// q_index: index of Q(t) in q_tape, or -1 outside the window.
+hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletSites& S, const void* A,
+                           const float* gin, float* gout, float omega, const float* alpha,
+                           double* alpha_hat, const float* wss_w, const float* normal, int64_t t,
+                           int32_t outlet, const double* q_tape, int64_t q_index,
+                           double q_target, double* theta_acc, int32_t nbasis, hipStream_t s);
+
+}  // namespace hlb

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/hemelb_lb.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -149,6 +150,43 @@ struct hemelb_lb {
 
     int64_t device_bytes = 0;
 
+    // host copies kept for runtime updates and the adjoint
+    std::vector<int32_t> order;     // Morton index -> caller index
+    std::vector<int32_t> h_gsite;   // ghost link -> Morton site
+    std::vector<uint8_t> h_gdir, h_giol;
+    std::vector<uint8_t> has_normal;  // per Morton site
+    struct HostIolet {
+        int kind, n_harm, harm_off;
+        double dir[3];
+    };
+    std::vector<HostIolet> h_iolets;
+    std::vector<double> h_harm;
+
+    // objective (outlet flux + dome wall shear over a window of steps)
+    bool obj_set = false;
+    int32_t obj_outlet = -1;
+    double q_target = 0, lam = 0;
+    int64_t w0 = 0, w1 = 0, n_dome = 0;
+    int32_t* d_out_links = nullptr;
+    int32_t n_out = 0;
+    int32_t* d_dome = nullptr;
+    float* d_wss_w = nullptr;
+    double* d_qtape = nullptr;
+    double* d_wtape = nullptr;
+
+    // adjoint
+    std::vector<void*> tape;  // K+1 population buffers of a recompute segment
+    float* ghat[2] = {nullptr, nullptr};
+    int gcur = 0;
+    double* alpha_hat = nullptr;
+    double* theta_acc = nullptr;
+    int32_t nbasis = 1;
+    int32_t* is_site = nullptr;
+    int32_t* is_lo = nullptr;
+    int32_t* is_hi = nullptr;
+    int64_t n_is = 0;
+    int64_t adj_t = -1;
+
     hlb::Layout layout() const {
         return hlb::Layout{q, storage, scaled, n, slots, tbl};
     }
@@ -183,10 +221,15 @@ int dev_upload(hemelb_lb* h, T** p, const std::vector<T>& v, const char* what) {
 void release(hemelb_lb* h) {
     if (!h) return;
     if (h->stream || true) (void)hipStreamSynchronize(h->stream);
-    void* ptrs[] = {h->A[0], h->A[1], h->tbl, h->g_site, h->g_dir, h->g_iolet, h->g_coef,
-                    h->d_iolets, h->d_harm, h->perm, h->normal, h->alpha, h->partial, h->tot,
-                    h->flag};
+    void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
+                    h->g_iolet,   h->g_coef,    h->d_iolets,   h->d_harm,    h->perm,
+                    h->normal,    h->alpha,     h->partial,    h->tot,       h->flag,
+                    h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
+                    h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
+                    h->is_lo,     h->is_hi};
     for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (void* p : h->tape)
         if (p) (void)hipFree(p);
     for (auto e : h->ev) (void)hipEventDestroy(e);
     delete h;
@@ -267,6 +310,13 @@ int do_step(hemelb_lb* h) {
     void* src = h->A[h->cur];
     void* dst = h->A[h->cur ^ 1];
     HIP_TRY(hlb::launch_ghost_fill(L, h->ghosts(), src, h->t, h->stream), "ghost fill");
+    if (h->obj_set && h->t >= h->w0 && h->t < h->w1) {
+        const hlb::Objective O{h->d_out_links, h->n_out, h->d_dome, (int32_t)h->n_dome};
+        HIP_TRY(hlb::launch_objective(L, h->ghosts(), src, O, h->normal, h->omega,
+                                      h->d_qtape + (h->t - h->w0), h->d_wtape + (h->t - h->w0),
+                                      h->stream),
+                "objective");
+    }
     const bool timed = h->ev_used + 2 <= (int64_t)h->ev.size() && h->ev_cap > 0;
     if (timed) HIP_TRY(hipEventRecord(h->ev[h->ev_used], h->stream), "event");
     HIP_TRY(hlb::launch_stream_collide(L, src, dst, h->omega, h->alpha, h->xcd_group, h->stream),
@@ -551,6 +601,16 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
 
     std::vector<int32_t> perm;
     if (d->coords) perm = order;
+    h->has_normal.assign(n, 0);
+    for (int64_t m = 0; m < n; ++m)
+        h->has_normal[m] = (nrm[m] != 0.f || nrm[(size_t)n + m] != 0.f || nrm[2 * (size_t)n + m] != 0.f);
+    for (int k = 0; k < d->n_iolets; ++k) {
+        const hemelb_iolet_t& io = d->iolets[k];
+        hemelb_lb::HostIolet hi{io.kind, io.n_harm, dio[k].harm_off,
+                                {io.direction[0], io.direction[1], io.direction[2]}};
+        h->h_iolets.push_back(hi);
+    }
+    h->h_harm = harm;
     std::vector<float> alpha;
     if (d->alpha) {
         alpha.resize(n);
@@ -612,6 +672,10 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         return hip_fail(e, "create sync");
     }
 #undef TRY
+    h->order = std::move(order);
+    h->h_gsite = std::move(gsite);
+    h->h_gdir = std::move(gdir);
+    h->h_giol = std::move(giol);
     *out = h;
     return HEMELB_OK;
 }
@@ -759,6 +823,275 @@ int hemelb_copy_probe(void* dst, const void* src, int64_t bytes, void* stream) {
     if (!dst || !src || bytes <= 0 || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return fail(HEMELB_EINVAL, "copy probe needs 16-byte aligned pointers and size");
     HIP_TRY(hlb::launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream)), "copy probe");
+    return HEMELB_OK;
+}
+
+int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
+    if (!h || !io) return fail(HEMELB_EINVAL, "NULL argument");
+    if (k < 0 || k >= (int32_t)h->h_iolets.size()) return fail(HEMELB_EINVAL, "no iolet %d", k);
+    hemelb_lb::HostIolet& hi = h->h_iolets[k];
+    if (io->kind != hi.kind || io->n_harm != hi.n_harm)
+        return fail(HEMELB_EINVAL, "iolet %d: kind and number of harmonics are fixed at create", k);
+    if (io->n_harm > 0 && (!io->cos_k || !io->sin_k || !(io->period > 0)))
+        return fail(HEMELB_EINVAL, "iolet %d: harmonics need cos_k, sin_k and period > 0", k);
+    if (!std::isfinite(io->mean)) return fail(HEMELB_EINVAL, "iolet %d: mean not finite", k);
+    for (int a = 0; a < 3; ++a)
+        if (io->kind == HEMELB_IOLET_VELOCITY && io->direction[a] != hi.dir[a])
+            return fail(HEMELB_EINVAL, "iolet %d: direction is fixed at create", k);
+    for (int m = 0; m < io->n_harm; ++m) {
+        if (!std::isfinite(io->cos_k[m]) || !std::isfinite(io->sin_k[m]))
+            return fail(HEMELB_EINVAL, "iolet %d: harmonic %d not finite", k, m);
+        h->h_harm[hi.harm_off + m] = io->cos_k[m];
+        h->h_harm[hi.harm_off + io->n_harm + m] = io->sin_k[m];
+    }
+    hlb::DevIolet dv{hi.kind == HEMELB_IOLET_PRESSURE ? 0 : 1, hi.n_harm, hi.harm_off, 0, io->mean,
+                     io->n_harm > 0 ? io->period : 1.0};
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    HIP_TRY(hipMemcpy(h->d_iolets + k, &dv, sizeof dv, hipMemcpyHostToDevice), "iolet upload");
+    if (!h->h_harm.empty())
+        HIP_TRY(hipMemcpy(h->d_harm, h->h_harm.data(), h->h_harm.size() * sizeof(double),
+                          hipMemcpyHostToDevice),
+                "harmonics upload");
+    return HEMELB_OK;
+}
+
+int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    if (!alpha) {
+        if (h->alpha) {
+            (void)hipFree(h->alpha);
+            h->device_bytes -= h->n * (int64_t)sizeof(float);
+            h->alpha = nullptr;
+        }
+        return HEMELB_OK;
+    }
+    for (int64_t s = 0; s < h->n; ++s)
+        if (!(alpha[s] >= 0.f && alpha[s] <= 1.f))
+            return fail(HEMELB_EINVAL, "alpha[%lld] outside [0, 1]", (long long)s);
+    if (h->n == 0) return HEMELB_OK;
+    std::vector<float> a(h->n);
+    for (int64_t m = 0; m < h->n; ++m) a[m] = alpha[h->order[m]];
+    if (!h->alpha) {
+        int rc = dev_alloc(h, &h->alpha, (size_t)h->n, "alpha");
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpy(h->alpha, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice),
+            "alpha upload");
+    return HEMELB_OK;
+}
+
+int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    for (void** p : {(void**)&h->d_out_links, (void**)&h->d_dome, (void**)&h->d_wss_w,
+                     (void**)&h->d_qtape, (void**)&h->d_wtape})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    h->obj_set = false;
+    h->adj_t = -1;
+    if (!obj) return HEMELB_OK;
+    if (obj->outlet < 0 || obj->outlet >= (int32_t)h->h_iolets.size())
+        return fail(HEMELB_EINVAL, "objective outlet %d is not an iolet", obj->outlet);
+    if (obj->t0 < 0 || obj->t1 < obj->t0) return fail(HEMELB_EINVAL, "bad objective window");
+    if (!std::isfinite(obj->q_target) || !std::isfinite(obj->lam))
+        return fail(HEMELB_EINVAL, "objective constants must be finite");
+    std::vector<int32_t> outl, dome;
+    for (int64_t l = 0; l < h->nghost; ++l)
+        if (h->h_giol[l] == obj->outlet) outl.push_back((int32_t)l);
+    std::vector<float> w;
+    if (obj->dome) {
+        for (int64_t m = 0; m < h->n; ++m)
+            if (obj->dome[h->order[m]] && h->has_normal[m]) dome.push_back((int32_t)m);
+        const int64_t W = obj->t1 - obj->t0;
+        if (!dome.empty() && W > 0) {
+            w.assign(h->n, 0.f);
+            const double wt = obj->lam / ((double)W * (double)dome.size());
+            for (int32_t m : dome) w[m] = (float)wt;
+        }
+    }
+    const size_t nw = (size_t)std::max<int64_t>(1, obj->t1 - obj->t0);
+    int rc;
+    if ((rc = dev_upload(h, &h->d_out_links, outl, "objective links"))) return rc;
+    if ((rc = dev_upload(h, &h->d_dome, dome, "objective dome"))) return rc;
+    if ((rc = dev_upload(h, &h->d_wss_w, w, "objective weights"))) return rc;
+    std::vector<double> zeros(nw, 0.0);
+    if ((rc = dev_upload(h, &h->d_qtape, zeros, "flux tape"))) return rc;
+    if ((rc = dev_upload(h, &h->d_wtape, zeros, "shear tape"))) return rc;
+    h->n_out = (int32_t)outl.size();
+    h->n_dome = (int64_t)dome.size();
+    h->obj_outlet = obj->outlet;
+    h->q_target = obj->q_target;
+    h->lam = obj->lam;
+    h->w0 = obj->t0;
+    h->w1 = obj->t1;
+    h->obj_set = true;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_objective_value(hemelb_lb_t h, double* J, double* flux_term, double* wss_term) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (!h->obj_set) return fail(HEMELB_EORDER, "no objective set");
+    if (h->t < h->w1)
+        return fail(HEMELB_EORDER, "the forward run (t = %lld) has not reached the window end %lld",
+                    (long long)h->t, (long long)h->w1);
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    const int64_t W = h->w1 - h->w0;
+    std::vector<double> q(std::max<int64_t>(W, 1)), w(std::max<int64_t>(W, 1));
+    HIP_TRY(hipMemcpy(q.data(), h->d_qtape, q.size() * sizeof(double), hipMemcpyDeviceToHost), "tape");
+    HIP_TRY(hipMemcpy(w.data(), h->d_wtape, w.size() * sizeof(double), hipMemcpyDeviceToHost), "tape");
+    double fl = 0, ws = 0;
+    for (int64_t k = 0; k < W; ++k) {
+        fl += (q[k] - h->q_target) * (q[k] - h->q_target);
+        ws += w[k];
+    }
+    if (W > 0 && h->n_dome > 0) ws *= h->lam / ((double)W * (double)h->n_dome);
+    else ws = 0;
+    if (J) *J = fl + ws;
+    if (flux_term) *flux_term = fl;
+    if (wss_term) *wss_term = ws;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_objective_flux(hemelb_lb_t h, double* q) {
+    if (!h || !q) return fail(HEMELB_EINVAL, "NULL argument");
+    if (!h->obj_set) return fail(HEMELB_EORDER, "no objective set");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    const int64_t W = h->w1 - h->w0;
+    if (W > 0)
+        HIP_TRY(hipMemcpy(q, h->d_qtape, W * sizeof(double), hipMemcpyDeviceToHost), "tape");
+    return HEMELB_OK;
+}
+
+int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (!h->obj_set) return fail(HEMELB_EORDER, "set an objective and run the forward first");
+    if (max_segment < 1) return fail(HEMELB_EINVAL, "max_segment must be >= 1");
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    const size_t popbytes = (size_t)h->q * h->slots * h->elem();
+    while ((int64_t)h->tape.size() < max_segment + 1) {
+        void* p = nullptr;
+        HIP_TRY(hipMalloc(&p, popbytes), "adjoint tape");
+        h->tape.push_back(p);
+        h->device_bytes += (int64_t)popbytes;
+    }
+    const size_t gcount = (size_t)h->q * h->slots;
+    int rc;
+    for (int b = 0; b < 2; ++b)
+        if (!h->ghat[b] && (rc = dev_alloc(h, &h->ghat[b], gcount, "adjoint state"))) return rc;
+    if (!h->alpha_hat && h->n > 0 && (rc = dev_alloc(h, &h->alpha_hat, (size_t)h->n, "alpha adjoint")))
+        return rc;
+    int32_t hmax = 0;
+    for (auto& io : h->h_iolets)
+        if (io.kind == HEMELB_IOLET_VELOCITY) hmax = std::max(hmax, io.n_harm);
+    h->nbasis = 1 + 2 * hmax;
+    if (!h->theta_acc && h->nghost > 0 &&
+        (rc = dev_alloc(h, &h->theta_acc, (size_t)h->nghost * h->nbasis, "theta adjoint")))
+        return rc;
+    if (!h->is_site && h->nghost > 0) {
+        std::vector<int32_t> st, lo, hi;
+        for (int64_t l = 0; l < h->nghost;) {
+            int64_t e = l;
+            while (e < h->nghost && h->h_gsite[e] == h->h_gsite[l]) ++e;
+            st.push_back(h->h_gsite[l]);
+            lo.push_back((int32_t)l);
+            hi.push_back((int32_t)e);
+            l = e;
+        }
+        if ((rc = dev_upload(h, &h->is_site, st, "iolet sites"))) return rc;
+        if ((rc = dev_upload(h, &h->is_lo, lo, "iolet sites"))) return rc;
+        if ((rc = dev_upload(h, &h->is_hi, hi, "iolet sites"))) return rc;
+        h->n_is = (int64_t)st.size();
+    }
+    h->gcur = 0;
+    hlb::Layout Lg = h->layout();
+    Lg.storage = HEMELB_STORE_F32;
+    HIP_TRY(hlb::launch_zero(Lg, h->ghat[0], h->stream), "adjoint zero");
+    if (h->alpha_hat) HIP_TRY(hlb::launch_zero_words(h->alpha_hat, 2 * h->n, h->stream), "zero");
+    if (h->theta_acc)
+        HIP_TRY(hlb::launch_zero_words(h->theta_acc, 2 * h->nghost * h->nbasis, h->stream), "zero");
+    h->adj_t = h->t;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (h->adj_t < 0) return fail(HEMELB_EORDER, "call hemelb_lb_adjoint_begin first");
+    if (steps < 1 || steps + 1 > (int64_t)h->tape.size())
+        return fail(HEMELB_EINVAL, "segment of %lld steps exceeds the tape (%lld)", (long long)steps,
+                    (long long)h->tape.size() - 1);
+    if (t0 < 0 || t0 + steps != h->adj_t)
+        return fail(HEMELB_EORDER, "segments must run backwards: expected one ending at %lld",
+                    (long long)h->adj_t);
+    if (!checkpoint && h->n > 0) return fail(HEMELB_EINVAL, "checkpoint is NULL");
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    const hlb::Layout L = h->layout();
+    const hlb::Ghosts G = h->ghosts();
+    HIP_TRY(hlb::launch_state(L, h->tape[0], const_cast<void*>(checkpoint), h->perm, 1, h->stream),
+            "checkpoint restore");
+    for (int64_t m = 0; m < steps; ++m) {
+        HIP_TRY(hlb::launch_ghost_fill(L, G, h->tape[m], t0 + m, h->stream), "recompute ghosts");
+        HIP_TRY(hlb::launch_stream_collide(L, h->tape[m], h->tape[m + 1], h->omega, h->alpha,
+                                           h->xcd_group, h->stream),
+                "recompute");
+    }
+    const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
+    for (int64_t m = steps - 1; m >= 0; --m) {
+        const int64_t t = t0 + m;
+        const bool inw = t >= h->w0 && t < h->w1;
+        HIP_TRY(hlb::launch_adj_step(L, G, S, h->tape[m], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
+                                     h->omega, h->alpha, h->alpha_hat, inw ? h->d_wss_w : nullptr,
+                                     h->normal, t, h->obj_outlet, h->d_qtape,
+                                     inw ? t - h->w0 : -1, h->q_target, h->theta_acc, h->nbasis,
+                                     h->stream),
+                "adjoint step");
+        h->gcur ^= 1;
+    }
+    h->adj_t = t0;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (h->adj_t < 0) return fail(HEMELB_EORDER, "no adjoint run");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    if (dalpha) {
+        std::vector<double> a(h->n, 0.0);
+        if (h->n > 0)
+            HIP_TRY(hipMemcpy(a.data(), h->alpha_hat, h->n * sizeof(double), hipMemcpyDeviceToHost),
+                    "alpha adjoint");
+        for (int64_t m = 0; m < h->n; ++m) dalpha[h->order[m]] = a[m];
+    }
+    if (dtheta) {
+        std::vector<double> acc((size_t)h->nghost * h->nbasis, 0.0);
+        if (!acc.empty())
+            HIP_TRY(hipMemcpy(acc.data(), h->theta_acc, acc.size() * sizeof(double),
+                              hipMemcpyDeviceToHost),
+                    "theta adjoint");
+        size_t off = 0;
+        for (size_t k = 0; k < h->h_iolets.size(); ++k) {
+            const auto& io = h->h_iolets[k];
+            if (io.kind != HEMELB_IOLET_VELOCITY) continue;
+            const int B = 1 + 2 * io.n_harm;
+            for (int b = 0; b < B; ++b) dtheta[off + b] = 0.0;
+            for (int64_t l = 0; l < h->nghost; ++l)
+                if (h->h_giol[l] == k)
+                    for (int b = 0; b < B; ++b) dtheta[off + b] += acc[(size_t)l * h->nbasis + b];
+            off += B;
+        }
+    }
+    return HEMELB_OK;
+}
+
+int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst) {
+    if (!h || (!dst && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
+    if (h->adj_t < 0) return fail(HEMELB_EORDER, "no adjoint run");
+    hlb::Layout Lg = h->layout();
+    Lg.storage = HEMELB_STORE_F32;
+    Lg.scaled = false;
+    HIP_TRY(hlb::launch_state(Lg, h->ghat[h->gcur], dst, h->perm, 0, h->stream), "adjoint get");
     return HEMELB_OK;
 }
 

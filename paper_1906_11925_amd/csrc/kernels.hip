@@ -20,78 +20,9 @@
 
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "lbdev.hpp"
 
 namespace hlb {
-
-template <int Q_, int ST_, bool SC_>
-struct Tag {
-    static constexpr int Q = Q_;
-    static constexpr int ST = ST_;
-    static constexpr bool SC = SC_;
-};
-
-template <class F>
-static hipError_t dispatch(int q, int st, bool scaled, F&& f) {
-    if (q == 15) {
-        if (st == ST_F32) return f(Tag<15, ST_F32, false>{});
-        if (st == ST_F16) return scaled ? f(Tag<15, ST_F16, true>{}) : f(Tag<15, ST_F16, false>{});
-        if (st == ST_BF16) return scaled ? f(Tag<15, ST_BF16, true>{}) : f(Tag<15, ST_BF16, false>{});
-    } else if (q == 19) {
-        if (st == ST_F32) return f(Tag<19, ST_F32, false>{});
-        if (st == ST_F16) return scaled ? f(Tag<19, ST_F16, true>{}) : f(Tag<19, ST_F16, false>{});
-        if (st == ST_BF16) return scaled ? f(Tag<19, ST_BF16, true>{}) : f(Tag<19, ST_BF16, false>{});
-    }
-    return hipErrorInvalidValue;
-}
-
-// element (direction i, site s) of a tiled array with R rows per tile
-template <int R>
-__device__ inline int64_t tix(int i, int32_t s) {
-    return ((int64_t)(s >> kTileShift) * R + i) * kTile + (s & (kTile - 1));
-}
-
-// decode a table entry for direction i: (source direction, source site)
-__device__ inline void link_src(int i, int32_t j, int& dir, int32_t& site) {
-    const bool wall = j < 0;
-    dir = wall ? opp(i) : i;
-    site = j & 0x7fffffff;
-}
-
-// moments of FP32 deviations: drho = sum d, m = sum c d (constant-folded per lattice)
-template <int Q>
-__device__ inline void moments(const float (&d)[Q], float& drho, float& mx, float& my, float& mz) {
-    using Lt = Lat<Q>;
-    drho = d[0];
-    mx = my = mz = 0.f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        drho += d[i];
-        if (Lt::cx[i] > 0) mx += d[i];
-        if (Lt::cx[i] < 0) mx -= d[i];
-        if (Lt::cy[i] > 0) my += d[i];
-        if (Lt::cy[i] < 0) my -= d[i];
-        if (Lt::cz[i] > 0) mz += d[i];
-        if (Lt::cz[i] < 0) mz -= d[i];
-    }
-}
-
-// equilibrium deviations deq_i = f_i^eq(rho, u) - w_i for all i (pairs share the
-// even part of the quadratic)
-template <int Q>
-__device__ inline void eq_dev(float drho, float rho, float ux, float uy, float uz,
-                              float (&deq)[Q]) {
-    using Lt = Lat<Q>;
-    const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-    deq[0] = Lt::w[0] * (drho - rho * usq15);
-#pragma unroll
-    for (int k = 1; k < Q; k += 2) {
-        const float cu = (float)Lt::cx[k] * ux + (float)Lt::cy[k] * uy + (float)Lt::cz[k] * uz;
-        const float sym = Lt::w[k] * (drho + rho * (4.5f * cu * cu - usq15));
-        const float asym = Lt::w[k] * rho * 3.0f * cu;
-        deq[k] = sym + asym;
-        deq[k + 1] = sym - asym;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // fused pull stream + LBGK collide
@@ -185,17 +116,6 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
 // ---------------------------------------------------------------------------
 // iolet ghost fill: the incoming population of every iolet link for this step
 // ---------------------------------------------------------------------------
-__device__ inline double iolet_value(const DevIolet& io, const double* harm, double t) {
-    double v = io.mean;
-    for (int h = 1; h <= io.n_harm; ++h) {
-        const double ph = fmod((double)h * t, io.period) / io.period;  // in [0, 1)
-        double sv, cv;
-        sincospi(2.0 * ph, &sv, &cv);
-        v += harm[io.harm_off + h - 1] * cv + harm[io.harm_off + io.n_harm + h - 1] * sv;
-    }
-    return v;
-}
-
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __restrict__ A,
                                                         Ghosts G, int32_t n, double t) {
@@ -494,6 +414,14 @@ hipError_t launch_zero(const Layout& L, void* A, hipStream_t s) {
     if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     k_zero<<<(unsigned)nb, kBlock, 0, s>>>(static_cast<uint32_t*>(A), words);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    int64_t nb = (words + kBlock - 1) / kBlock;
+    if (nb > 4096) nb = 4096;
+    k_zero<<<(unsigned)nb, kBlock, 0, s>>>(static_cast<uint32_t*>(p), words);
     return hipGetLastError();
 }
 

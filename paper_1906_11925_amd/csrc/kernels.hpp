@@ -70,4 +70,7 @@ hipError_t launch_zero(const Layout& L, void* A, hipStream_t s);
 
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 
+// fill `words` 32-bit words with zero
+hipError_t launch_zero_words(void* p, int64_t words, hipStream_t s);
+
 }  // namespace hlb

@@ -98,6 +98,7 @@ class LB:
         h = ctypes.c_void_p()
         L.check(self.lib.hemelb_lb_create(ctypes.byref(h), ctypes.byref(d)))
         self.h = h
+        self.iolets = list(iolets)
         del keep
 
     @classmethod
@@ -189,6 +190,96 @@ class LB:
             raise ValueError("deviations must be [Q, N]")
         L.check(self.lib.hemelb_lb_set_deviations(self.h, ctypes.c_void_p(src.data_ptr()), int(t)))
         self._keep = src
+
+    # -- parameters, objective and adjoint -------------------------------------------
+    def set_iolet(self, k, io):
+        """Replace iolet k's time series (same kind, harmonics count and direction)."""
+        cos = np.ascontiguousarray(getattr(io, "cos", ()), dtype=np.float64)
+        sin = np.ascontiguousarray(getattr(io, "sin", ()), dtype=np.float64)
+        t = L.IoletT()
+        t.kind = L.IOLET_PRESSURE if io.kind == "pressure" else L.IOLET_VELOCITY
+        for a in range(3):
+            t.direction[a] = float(io.direction[a])
+        t.mean = float(io.mean)
+        t.n_harm = int(cos.size)
+        t.cos_k = _ptr(cos, L.c_double) if cos.size else None
+        t.sin_k = _ptr(sin, L.c_double) if sin.size else None
+        t.period = float(getattr(io, "period", 1.0))
+        L.check(self.lib.hemelb_lb_set_iolet(self.h, int(k), ctypes.byref(t)))
+        self.iolets[k] = io
+
+    def set_alpha(self, alpha):
+        if alpha is None:
+            L.check(self.lib.hemelb_lb_set_alpha(self.h, None))
+            return
+        a = np.ascontiguousarray(alpha, dtype=np.float32)
+        if a.shape != (self.n,):
+            raise ValueError("alpha must be [N]")
+        L.check(self.lib.hemelb_lb_set_alpha(self.h, _ptr(a, L.c_float)))
+
+    def set_objective(self, outlet, q_target, dome, lam, window):
+        """J = sum_{t in window} (Q(t) - q_target)^2 + lam * mean_t mean_{dome} WSS."""
+        o = L.ObjectiveT()
+        o.outlet = int(outlet)
+        o.q_target = float(q_target)
+        self._dome = None
+        if dome is not None:
+            self._dome = np.ascontiguousarray(dome, dtype=np.uint8)
+            if self._dome.shape != (self.n,):
+                raise ValueError("dome must be [N]")
+            o.dome = _ptr(self._dome, ctypes.c_uint8)
+        o.lam = float(lam)
+        o.t0, o.t1 = int(window[0]), int(window[1])
+        self.window = (o.t0, o.t1)
+        L.check(self.lib.hemelb_lb_set_objective(self.h, ctypes.byref(o)))
+
+    def clear_objective(self):
+        L.check(self.lib.hemelb_lb_set_objective(self.h, None))
+
+    def objective_value(self):
+        """(J, flux term, shear term) in FP64."""
+        v = [ctypes.c_double(0) for _ in range(3)]
+        L.check(self.lib.hemelb_lb_objective_value(self.h, *(ctypes.byref(x) for x in v)))
+        return tuple(x.value for x in v)
+
+    def objective_flux(self):
+        q = np.zeros(max(1, self.window[1] - self.window[0]))
+        L.check(self.lib.hemelb_lb_objective_flux(self.h, _ptr(q, L.c_double)))
+        return q[: self.window[1] - self.window[0]]
+
+    def adjoint_begin(self, max_segment):
+        L.check(self.lib.hemelb_lb_adjoint_begin(self.h, int(max_segment)))
+
+    def adjoint_segment(self, checkpoint, t0, steps):
+        checkpoint = checkpoint.contiguous()
+        if checkpoint.dtype != self._raw_dtype() or tuple(checkpoint.shape) != (self.q, self.n):
+            raise ValueError("checkpoint must be a raw state [Q, N]")
+        L.check(self.lib.hemelb_lb_adjoint_segment(self.h, ctypes.c_void_p(checkpoint.data_ptr()),
+                                                   int(t0), int(steps)))
+        self._keep = checkpoint
+
+    def theta_sizes(self):
+        """Number of Fourier coefficients of each velocity iolet, in id order."""
+        return [(k, 1 + 2 * len(getattr(io, "cos", ()))) for k, io in enumerate(self.iolets)
+                if io.kind == "velocity"]
+
+    def adjoint_grads(self):
+        """({velocity iolet k: dJ/d(mean, cos_h, sin_h)}, dJ/dalpha [N]) in FP64."""
+        sizes = self.theta_sizes()
+        th = np.zeros(max(1, sum(b for _, b in sizes)))
+        da = np.zeros(max(1, self.n))
+        L.check(self.lib.hemelb_lb_adjoint_grads(self.h, _ptr(th, L.c_double), _ptr(da, L.c_double)))
+        out, off = {}, 0
+        for k, b in sizes:
+            out[k] = th[off:off + b].copy()
+            off += b
+        return out, da[: self.n]
+
+    def get_adjoint(self):
+        torch = _torch()
+        dst = torch.empty((self.q, self.n), dtype=torch.float32, device="cuda")
+        L.check(self.lib.hemelb_lb_get_adjoint(self.h, ctypes.c_void_p(dst.data_ptr())))
+        return dst
 
     # -- timing -------------------------------------------------------------------
     def kernel_timing(self, max_launches):

@@ -51,6 +51,11 @@ class InfoT(ctypes.Structure):
                 ("bytes_per_update", c_int64), ("device_bytes", c_int64)]
 
 
+class ObjectiveT(ctypes.Structure):
+    _fields_ = [("outlet", c_int32), ("q_target", c_double), ("dome", P(ctypes.c_uint8)),
+                ("lam", c_double), ("t0", c_int64), ("t1", c_int64)]
+
+
 class HemelbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"hemelb error {code}: {msg}")
@@ -79,6 +84,15 @@ _SIGS = {
     "hemelb_lb_kernel_timing": (c_int32, [c_void_p, c_int64]),
     "hemelb_lb_kernel_time": (c_int32, [c_void_p, P(c_double), P(c_int64)]),
     "hemelb_copy_probe": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "hemelb_lb_set_iolet": (c_int32, [c_void_p, c_int32, P(IoletT)]),
+    "hemelb_lb_set_alpha": (c_int32, [c_void_p, P(c_float)]),
+    "hemelb_lb_set_objective": (c_int32, [c_void_p, P(ObjectiveT)]),
+    "hemelb_lb_objective_value": (c_int32, [c_void_p, P(c_double), P(c_double), P(c_double)]),
+    "hemelb_lb_objective_flux": (c_int32, [c_void_p, P(c_double)]),
+    "hemelb_lb_adjoint_begin": (c_int32, [c_void_p, c_int64]),
+    "hemelb_lb_adjoint_segment": (c_int32, [c_void_p, c_void_p, c_int64, c_int64]),
+    "hemelb_lb_adjoint_grads": (c_int32, [c_void_p, P(c_double), P(c_double)]),
+    "hemelb_lb_get_adjoint": (c_int32, [c_void_p, c_void_p]),
     "hemelb_lb_last_error": (ctypes.c_char_p, []),
     "hemelb_lb_strerror": (ctypes.c_char_p, [c_int32]),
 }

@@ -1,0 +1,144 @@
+"""GPU adjoint (HIP kernels through the C ABI) against the FP64 oracle's adjoint.
+
+The oracle's adjoint is pinned to central finite differences of the FP64
+forward (tests/test_oracle_adjoint.py).  Here the GPU's FP32 forward objective
+and its FP32-adjoint / FP64-accumulated gradients are compared with it:
+
+* J and the recorded outlet flux Q(t): relative error <= 1e-5;
+* gradients w.r.t. the inlet's Fourier coefficients and the Brinkman field:
+  max |g_gpu - g_ref| / max |g_ref| <= 1e-4 (the stated adjoint tolerance);
+* the adjoint populations dJ/dA_0 likewise;
+* checkpoint segmentation does not change the result (bit-exact);
+* the autograd.Function returns the same gradients.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as wl  # noqa: E402
+from oracle.lbgk import LBGK  # noqa: E402
+from oracle.adjoint import Adjoint, Objective  # noqa: E402
+from paper_1906_11925_amd import LB  # noqa: E402
+from paper_1906_11925_amd.autograd import LBAdjointFn  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def tiny_vessel(tau=0.7):
+    return wl.pipe(X=8, Y=8, Z=12, r2=9.0, tau=tau,
+                   inlet_velocity=(0.02, (0.0, 0.003), (0.01, 0.002), 40.0))
+
+
+def _problem(g, T, W, seed=4, amax=0.01, dome_fn=None):
+    n = g.n_sites
+    alpha = np.random.default_rng(seed).uniform(0.0, amax, n).astype(np.float32).astype(np.float64)
+    o = LBGK(g, 15, alpha=alpha)
+    _, has = o.wall_normals()
+    dome = has & dome_fn(g.coords)
+    nominal = Adjoint(o, Objective(1, 0.0, dome, 0.0, W))
+    _, _, qs = nominal.forward(o.rest_state(), T)
+    q_target = 0.9 * qs.mean()
+    lam = 1.0
+    adj = Adjoint(o, Objective(1, q_target, dome, lam, W))
+    J, tape, qref = adj.forward(o.rest_state(), T)
+    flux = np.sum((qref - q_target) ** 2)
+    lam = flux / max(J - flux, 1e-300)  # shear term equal to the flux term
+    obj = Objective(1, q_target, dome, lam, W)
+    adj = Adjoint(o, obj)
+    J, tape, qref = adj.forward(o.rest_state(), T)
+    theta, ahat, g0 = adj.backward(tape, T)
+    return dict(g=g, o=o, obj=obj, alpha=alpha, dome=dome, J=J, q=qref, theta=theta[0],
+                ahat=ahat, g0=g0, T=T)
+
+
+def _gpu_run(P, K):
+    g, obj = P["g"], P["obj"]
+    lb = LB.from_geometry(g, alpha=P["alpha"].astype(np.float32))
+    lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+    T = P["T"]
+    cks = []
+    for t0 in range(0, T, K):
+        cks.append((t0, min(K, T - t0), lb.get_state()[0].clone()))
+        lb.step(min(K, T - t0))
+    J = lb.objective_value()
+    q = lb.objective_flux()
+    lb.adjoint_begin(K)
+    for t0, k, ck in reversed(cks):
+        lb.adjoint_segment(ck, t0, k)
+    th, da = lb.adjoint_grads()
+    g0 = lb.get_adjoint().cpu().numpy().astype(np.float64)
+    return J, q, th[0], da, g0
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _problem(tiny_vessel(), 40, (25, 40), dome_fn=lambda c: (c[:, 2] >= 4) & (c[:, 2] <= 7))
+
+
+def test_objective_matches_oracle(tiny):
+    _gpu()
+    (J, fl, ws), q, _, _, _ = _gpu_run(tiny, 40)
+    assert abs(J - tiny["J"]) <= 1e-5 * abs(tiny["J"])
+    assert _rel(q, tiny["q"]) <= 1e-5
+
+
+@pytest.mark.parametrize("K", [40, 7])
+def test_gradients_match_oracle_adjoint(tiny, K):
+    _gpu()
+    _, _, th, da, g0 = _gpu_run(tiny, K)
+    et, ea, eg = _rel(th, tiny["theta"]), _rel(da, tiny["ahat"]), _rel(g0, tiny["g0"])
+    print(f"tiny K={K}: e_theta={et:.2e} e_alpha={ea:.2e} e_A0={eg:.2e}", flush=True)
+    assert et <= 1e-4 and ea <= 1e-4 and eg <= 1e-4
+
+
+def test_segmentation_is_exact(tiny):
+    _gpu()
+    a = _gpu_run(tiny, 40)
+    b = _gpu_run(tiny, 7)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_autograd_function(tiny):
+    _gpu()
+    g, obj = tiny["g"], tiny["obj"]
+    lb = LB.from_geometry(g, alpha=tiny["alpha"].astype(np.float32))
+    lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+    io = g.iolets[0]
+    theta = torch.tensor([io.mean, *io.cos, *io.sin], dtype=torch.float64, requires_grad=True)
+    alpha = torch.tensor(tiny["alpha"], dtype=torch.float64, requires_grad=True)
+    J = LBAdjointFn.apply(theta, alpha, lb, 0, tiny["T"], 9)
+    (2.0 * J).backward()
+    assert abs(J.item() - tiny["J"]) <= 1e-5 * abs(tiny["J"])
+    assert _rel(theta.grad.numpy() / 2.0, tiny["theta"]) <= 1e-4
+    assert _rel(alpha.grad.numpy() / 2.0, tiny["ahat"]) <= 1e-4
+
+
+def test_aneurysm_half_truncated_vs_oracle():
+    """The adjoint workload's geometry (half-size aneurysm, pulsatile Ladd inlet,
+    Brinkman field), truncated to 60 steps with a 20-step window."""
+    _gpu()
+    g = wl.aneurysm(half=True)
+    C, R, r = g.info["centre"], g.info["radius"], g.info["r"]
+
+    def dome_fn(c):
+        return ((c[:, 0] - C[0]) ** 2 + (c[:, 1] - C[1]) ** 2 + (c[:, 2] - C[2]) ** 2) < (R + 2) ** 2
+
+    P = _problem(g, 60, (40, 60), dome_fn=dome_fn)
+    (J, _, _), q, th, da, g0 = _gpu_run(P, 20)
+    et, ea = _rel(th, P["theta"]), _rel(da, P["ahat"])
+    print(f"aneurysm_half: J rel {abs(J - P['J']) / P['J']:.2e} e_theta={et:.2e} e_alpha={ea:.2e}",
+          flush=True)
+    assert abs(J - P["J"]) <= 1e-5 * abs(P["J"])
+    assert et <= 1e-4 and ea <= 1e-4
