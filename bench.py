@@ -86,6 +86,59 @@ def cpu_baseline(geom, lattice, nsteps):
                       f"FP64 NumPy, single thread"}
 
 
+def adjoint_run(steps=4000, K=200, window=1000):
+    """Adjoint workload: half-size aneurysm (199,360 sites), FP32 forward, outlet
+    flux + dome wall-shear objective over the last `window` steps, gradients with
+    respect to the inlet's Fourier coefficients and a Brinkman field, checkpoints
+    every K steps.  Returns timing of the forward and of the reverse sweep
+    (recompute + adjoint kernels)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1906_11925_amd import LB
+    g = wl.aneurysm(half=True)
+    n = g.n_sites
+    c = g.coords.astype(np.float64)
+    C, R = g.info["centre"], g.info["radius"]
+    dome = ((c[:, 0] - C[0]) ** 2 + (c[:, 1] - C[1]) ** 2 + (c[:, 2] - C[2]) ** 2) < (R + 2) ** 2
+    alpha = np.random.default_rng(4).uniform(0.0, 0.01, n).astype(np.float32)
+    lb = LB.from_geometry(g, alpha=alpha)
+    W = (steps - window, steps)
+    lb.set_objective(1, 0.0, dome, 1.0, W)
+
+    def forward():
+        lb.set_deviations(torch.zeros((lb.q, n), dtype=torch.float32, device="cuda"), t=0)
+        cks = []
+        for t0 in range(0, steps, K):
+            cks.append((t0, min(K, steps - t0), lb.get_state()[0].clone()))
+            lb.step(min(K, steps - t0))
+        lb.sync()
+        return cks
+
+    forward()
+    q = lb.objective_flux()
+    lb.set_objective(1, 0.9 * float(q.mean()), dome, 1.0, W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cks = forward()
+    t_fwd = time.perf_counter() - t0
+    J = lb.objective_value()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.adjoint_begin(K)
+    for s0, k, ck in reversed(cks):
+        lb.adjoint_segment(ck, s0, k)
+    th, da = lb.adjoint_grads()
+    t_bwd = time.perf_counter() - t0
+    lb.close()
+    return {"workload": "aneurysm_half", "sites": n, "steps": steps, "checkpoint_every": K,
+            "window": window, "J": J[0], "forward_s": t_fwd, "reverse_s": t_bwd,
+            "adjoint_GLUPS": n * steps / t_bwd / 1e9,
+            "forward_GLUPS_with_objective": n * steps / t_fwd / 1e9,
+            "dJ_dtheta": [float(x) for x in th[0]],
+            "dJ_dalpha_norm": float(np.linalg.norm(da))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,7 +148,7 @@ def main():
     ap.add_argument("--lattice", type=int, default=15)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps for cpu_baseline (0: skip)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and adjoint runs")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed stream+collide steps (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -184,6 +237,9 @@ def main():
                          "speedup_vs_" + args.storage: dt / d}
             log(f"[bench] {st}: {extra[st]['GLUPS']:.2f} GLUPS")
             x.close()
+        log("[bench] adjoint workload")
+        extra["adjoint"] = adjoint_run()
+        log(f"[bench] adjoint: {extra['adjoint']['adjoint_GLUPS']:.3f} GLUPS (reverse incl. recompute)")
 
     cpu = None
     if args.cpu_steps > 0:

@@ -141,7 +141,8 @@ typedef struct {
     int64_t time;        /* completed steps (boundary time of the next step) */
     int32_t lattice;
     int32_t storage;
-    int64_t bytes_per_update; /* algorithmic HBM bytes of one site update (pops r+w + table) */
+    double bytes_per_update;  /* algorithmic HBM bytes of one site update: populations read
+                                 and written once plus the neighbour table */
     int64_t device_bytes;     /* device memory held by the handle */
 } hemelb_lb_info_t;
 

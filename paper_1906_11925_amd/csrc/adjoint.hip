@@ -35,14 +35,12 @@ namespace hlb {
 
 constexpr int kObjBlock = 1024;
 
-// pre-collision populations (deviations) of site s from a state with filled ghosts
+// pre-collision populations (deviations) of site s from a state with filled
+// ghosts, given its decoded links j
 template <int Q, int ST, bool SC>
-__device__ inline void gather_pre(const typename Store<ST>::T* __restrict__ A,
-                                  const int32_t* __restrict__ tbl, int32_t s, float (&d)[Q],
-                                  int32_t (&j)[Q]) {
+__device__ inline void gather_pre(const typename Store<ST>::T* __restrict__ A, int32_t s,
+                                  float (&d)[Q], int32_t (&j)[Q]) {
     using C = Codec<Q, ST, SC>;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) j[i] = tbl[tix<Q - 1>(i - 1, s)];
     j[0] = s;
     d[0] = C::dec(0, A[tix<Q>(0, s)]);
 #pragma unroll
@@ -103,7 +101,7 @@ __device__ inline double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kObjBlock) void k_objective(
-    const typename Store<ST>::T* __restrict__ A, const int32_t* __restrict__ tbl, int32_t n,
+    const typename Store<ST>::T* __restrict__ A, Table tb, int32_t n,
     Ghosts G, const int32_t* __restrict__ out_links, int32_t n_out,
     const int32_t* __restrict__ dome, int32_t n_dome, const float* __restrict__ normal,
     float omega, double* __restrict__ q_out, double* __restrict__ w_out) {
@@ -121,7 +119,9 @@ __global__ __launch_bounds__(kObjBlock) void k_objective(
         const int32_t s = dome[k];
         float d[Q];
         int32_t j[Q];
-        gather_pre<Q, ST, SC>(A, tbl, s, d, j);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) j[i] = link_one<Q>(tb, s, i);
+        gather_pre<Q, ST, SC>(A, s, d, j);
         float drho, mx, my, mz;
         moments<Q>(d, drho, mx, my, mz);
         const float ir = 1.0f / (1.0f + drho);
@@ -144,15 +144,17 @@ __global__ __launch_bounds__(kObjBlock) void k_objective(
 template <int Q, int ST, bool SC, bool BRINK>
 __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
-    float* __restrict__ gout, const int32_t* __restrict__ tbl, int32_t n, float omega,
+    float* __restrict__ gout, Table tb, int32_t n, float omega,
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal) {
     using Lt = Lat<Q>;
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n) return;
+    if ((s & ~(kTile - 1)) >= n) return;
     float d[Q];
     int32_t j[Q];
-    gather_pre<Q, ST, SC>(A, tbl, s, d, j);
+    links_wave<Q, false>(tb, s, j);
+    if (s >= n) return;
+    gather_pre<Q, ST, SC>(A, s, d, j);
     float g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = gin[tix<Q>(i, s)];
@@ -307,7 +309,7 @@ hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, con
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_objective<Tg::Q, Tg::ST, Tg::SC><<<1, kObjBlock, 0, s>>>(
-            static_cast<const T*>(A), L.tbl, (int32_t)L.n, G, O.out_links, O.n_out, O.dome,
+            static_cast<const T*>(A), L.tb, (int32_t)L.n, G, O.out_links, O.n_out, O.dome,
             O.n_dome, normal, omega, q_out, w_out);
         return hipGetLastError();
     });
@@ -324,11 +326,11 @@ hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletSites& S
         using T = typename Store<Tg::ST>::T;
         if (alpha)
             k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, true><<<blocks(L.n), kBlock, 0, s>>>(
-                static_cast<const T*>(A), gin, gout, L.tbl, (int32_t)L.n, omega, alpha, alpha_hat,
+                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, alpha, alpha_hat,
                 wss_w, normal);
         else
             k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, false><<<blocks(L.n), kBlock, 0, s>>>(
-                static_cast<const T*>(A), gin, gout, L.tbl, (int32_t)L.n, omega, nullptr,
+                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
                 alpha_hat, wss_w, normal);
         return hipGetLastError();
     });

@@ -124,13 +124,21 @@ struct hemelb_lb {
 
     void* A[2] = {nullptr, nullptr};
     int cur = 0;  // A[cur] holds the current post-collision state
-    int32_t* tbl = nullptr;
+    int32_t* tbl = nullptr;     // int32 table (when the compact one does not apply)
+    uint16_t* t16 = nullptr;    // compact table
+    int32_t* toff = nullptr;
+    int32_t* tlist = nullptr;
+    int64_t tlist_len = 0;
     int32_t* g_site = nullptr;
     uint8_t* g_dir = nullptr;
     uint8_t* g_iolet = nullptr;
     float* g_coef = nullptr;
     hlb::DevIolet* d_iolets = nullptr;
     double* d_harm = nullptr;
+    int32_t n_iolets = 0;
+    double* d_vals = nullptr;  // iolet values for a batch of steps
+    int64_t vals_cap = 0;      // steps the buffer holds
+    int64_t vals_t0 = 0;
     int32_t* perm = nullptr;  // Morton index -> caller index (null: identity)
     float* normal = nullptr;  // [3][n] Morton order
     float* alpha = nullptr;
@@ -141,6 +149,7 @@ struct hemelb_lb {
 
     int64_t t = 0;
     bool streamed = false;
+    bool ghosts_ready = false;  // A[cur]'s ghost slots hold the incoming values for time t
     int xcd_group = 16;  // consecutive 256-site blocks per XCD (measured best at 8-16)
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
@@ -188,12 +197,23 @@ struct hemelb_lb {
     int64_t adj_t = -1;
 
     hlb::Layout layout() const {
-        return hlb::Layout{q, storage, scaled, n, slots, tbl};
+        return hlb::Layout{q, storage, scaled, n, slots, hlb::Table{tbl, t16, toff, tlist}};
     }
     hlb::Ghosts ghosts() const {
-        return hlb::Ghosts{nghost, g_site, g_dir, g_iolet, g_coef, d_iolets, d_harm};
+        return hlb::Ghosts{nghost,  g_site, g_dir,   g_iolet,  g_coef,
+                           d_iolets, d_harm, d_vals, vals_t0, n_iolets};
     }
     size_t elem() const { return storage == HEMELB_STORE_F32 ? 4 : 2; }
+    // algorithmic HBM bytes of one site update: populations read and written once,
+    // plus the neighbour table (and the compact table's per-tile lists)
+    double bytes_per_update() const {
+        double b = 2.0 * q * (double)elem();
+        if (t16)
+            b += 2.0 * (q - 1) + (n > 0 ? 4.0 * (double)(tlist_len + ttiles + 1) / (double)n : 0.0);
+        else
+            b += 4.0 * (q - 1);
+        return b;
+    }
 };
 
 namespace {
@@ -222,11 +242,12 @@ void release(hemelb_lb* h) {
     if (!h) return;
     if (h->stream || true) (void)hipStreamSynchronize(h->stream);
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
+                    h->t16,       h->toff,      h->tlist,
                     h->g_iolet,   h->g_coef,    h->d_iolets,   h->d_harm,    h->perm,
                     h->normal,    h->alpha,     h->partial,    h->tot,       h->flag,
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
-                    h->is_lo,     h->is_hi};
+                    h->is_lo,     h->is_hi,     h->d_vals};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (void* p : h->tape)
@@ -305,11 +326,34 @@ int validate(const hemelb_lb_desc_t* d) {
     return HEMELB_OK;
 }
 
+// iolet values for times t0 .. t0 + count - 1 into the handle's table
+int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
+    if (h->n_iolets == 0) return HEMELB_OK;
+    if (count > h->vals_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+        if (h->d_vals) {
+            (void)hipFree(h->d_vals);
+            h->device_bytes -= h->vals_cap * h->n_iolets * (int64_t)sizeof(double);
+            h->d_vals = nullptr;
+        }
+        const int64_t cap = std::max<int64_t>(count, 1025);
+        int rc = dev_alloc(h, &h->d_vals, (size_t)(cap * h->n_iolets), "iolet values");
+        if (rc) return rc;
+        h->vals_cap = cap;
+    }
+    HIP_TRY(hlb::launch_iolet_series(h->d_iolets, h->d_harm, h->n_iolets, t0, count, h->d_vals,
+                                     h->stream),
+            "iolet series");
+    h->vals_t0 = t0;
+    return HEMELB_OK;
+}
+
 int do_step(hemelb_lb* h) {
     const hlb::Layout L = h->layout();
     void* src = h->A[h->cur];
     void* dst = h->A[h->cur ^ 1];
-    HIP_TRY(hlb::launch_ghost_fill(L, h->ghosts(), src, h->t, h->stream), "ghost fill");
+    if (!h->ghosts_ready)
+        HIP_TRY(hlb::launch_ghost_fill(L, h->ghosts(), src, h->t, h->stream), "ghost fill");
     if (h->obj_set && h->t >= h->w0 && h->t < h->w1) {
         const hlb::Objective O{h->d_out_links, h->n_out, h->d_dome, (int32_t)h->n_dome};
         HIP_TRY(hlb::launch_objective(L, h->ghosts(), src, O, h->normal, h->omega,
@@ -319,7 +363,8 @@ int do_step(hemelb_lb* h) {
     }
     const bool timed = h->ev_used + 2 <= (int64_t)h->ev.size() && h->ev_cap > 0;
     if (timed) HIP_TRY(hipEventRecord(h->ev[h->ev_used], h->stream), "event");
-    HIP_TRY(hlb::launch_stream_collide(L, src, dst, h->omega, h->alpha, h->xcd_group, h->stream),
+    HIP_TRY(hlb::launch_stream_collide(L, h->ghosts(), src, dst, h->omega, h->alpha, h->xcd_group,
+                                       h->t + 1, h->stream),
             "stream collide");
     if (timed) {
         HIP_TRY(hipEventRecord(h->ev[h->ev_used + 1], h->stream), "event");
@@ -328,6 +373,7 @@ int do_step(hemelb_lb* h) {
     h->cur ^= 1;
     h->t += 1;
     h->streamed = true;
+    h->ghosts_ready = hlb::ghosts_fused();
     if (h->check_every > 0 && h->t % h->check_every == 0)
         HIP_TRY(hlb::launch_totals(L, h->A[h->cur], h->partial, h->nparts, h->tot, h->flag,
                                    h->stream),
@@ -611,6 +657,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         h->h_iolets.push_back(hi);
     }
     h->h_harm = harm;
+    h->n_iolets = d->n_iolets;
     std::vector<float> alpha;
     if (d->alpha) {
         alpha.resize(n);
@@ -636,7 +683,57 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         h->A[b] = p;
         h->device_bytes += (int64_t)popbytes;
     }
-    TRY(dev_upload(h, &h->tbl, tbl, "neighbour table"));
+    // compact form: 16-bit codes against a per-tile list of source tiles
+    {
+        bool compact = true;
+        if (const char* e = getenv("HEMELB_TABLE")) compact = atoi(e) != 32;
+        std::vector<uint16_t> t16;
+        std::vector<int32_t> toff, tlist;
+        if (compact) {
+            t16.assign(tbl.size(), 0);
+            toff.assign((size_t)h->ttiles + 1, 0);
+            std::vector<int32_t> tiles;
+            for (int64_t T = 0; T < h->ttiles && compact; ++T) {
+                tiles.clear();
+                const size_t base = (size_t)T * (q - 1) * hlb::kTile;
+                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
+                    const int32_t v = tbl[base + e];
+                    if (v >= 0) tiles.push_back(v >> hlb::kTileShift);
+                }
+                std::sort(tiles.begin(), tiles.end());
+                tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+                if (tiles.size() > 2 * (size_t)hlb::kTile) {
+                    compact = false;
+                    break;
+                }
+                toff[T] = (int32_t)tlist.size();
+                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
+                    const int32_t v = tbl[base + e];
+                    uint16_t c;
+                    if (v < 0) {
+                        c = 0x8000u;
+                    } else {
+                        const int32_t slot = (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
+                                                                        v >> hlb::kTileShift) -
+                                                       tiles.begin());
+                        c = (uint16_t)((slot << hlb::kTileShift) | (v & (hlb::kTile - 1)));
+                    }
+                    t16[base + e] = c;
+                }
+                tlist.insert(tlist.end(), tiles.begin(), tiles.end());
+            }
+            toff[h->ttiles] = (int32_t)tlist.size();
+        }
+        if (compact) {
+            TRY(dev_upload(h, &h->t16, t16, "compact table"));
+            TRY(dev_upload(h, &h->toff, toff, "table tile offsets"));
+            if (tlist.empty()) tlist.push_back(0);
+            TRY(dev_upload(h, &h->tlist, tlist, "table tile lists"));
+            h->tlist_len = (int64_t)tlist.size();
+        } else {
+            TRY(dev_upload(h, &h->tbl, tbl, "neighbour table"));
+        }
+    }
     TRY(dev_upload(h, &h->g_site, gsite, "ghost sites"));
     TRY(dev_upload(h, &h->g_dir, gdir, "ghost dirs"));
     TRY(dev_upload(h, &h->g_iolet, giol, "ghost iolets"));
@@ -690,11 +787,14 @@ int hemelb_lb_step(hemelb_lb_t h, int64_t n) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (n < 0) return fail(HEMELB_EINVAL, "negative step count");
     HIP_TRY(hipSetDevice(h->device), "set device");
+    constexpr int64_t kBatch = 1024;  // steps per table of iolet values
     for (int64_t k = 0; k < n; ++k) {
         if (h->cancel.exchange(false))
             return fail(HEMELB_ECANCELLED, "cancelled after %lld of %lld steps", (long long)k,
                         (long long)n);
-        int rc = do_step(h);
+        int rc;
+        if (k % kBatch == 0 && (rc = fill_series(h, h->t, std::min(kBatch, n - k) + 1))) return rc;
+        rc = do_step(h);
         if (rc) return rc;
     }
     return HEMELB_OK;
@@ -762,6 +862,7 @@ int hemelb_lb_set_state(hemelb_lb_t h, const void* src, int64_t t) {
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
     h->t = t;
     h->streamed = false;
+    h->ghosts_ready = false;
     return state_io(h, const_cast<void*>(src), 1);
 }
 
@@ -775,6 +876,7 @@ int hemelb_lb_set_deviations(hemelb_lb_t h, const float* src, int64_t t) {
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
     h->t = t;
     h->streamed = false;
+    h->ghosts_ready = false;
     return state_io(h, const_cast<float*>(src), 3);
 }
 
@@ -786,7 +888,7 @@ int hemelb_lb_info(hemelb_lb_t h, hemelb_lb_info_t* info) {
     info->time = h->t;
     info->lattice = h->q;
     info->storage = h->storage;
-    info->bytes_per_update = (int64_t)(2 * h->q * h->elem() + 4 * (h->q - 1));
+    info->bytes_per_update = h->bytes_per_update();
     info->device_bytes = h->device_bytes;
     return HEMELB_OK;
 }
@@ -847,6 +949,7 @@ int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
     hlb::DevIolet dv{hi.kind == HEMELB_IOLET_PRESSURE ? 0 : 1, hi.n_harm, hi.harm_off, 0, io->mean,
                      io->n_harm > 0 ? io->period : 1.0};
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    h->ghosts_ready = false;
     HIP_TRY(hipMemcpy(h->d_iolets + k, &dv, sizeof dv, hipMemcpyHostToDevice), "iolet upload");
     if (!h->h_harm.empty())
         HIP_TRY(hipMemcpy(h->d_harm, h->h_harm.data(), h->h_harm.size() * sizeof(double),
@@ -1027,14 +1130,18 @@ int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0,
                     (long long)h->adj_t);
     if (!checkpoint && h->n > 0) return fail(HEMELB_EINVAL, "checkpoint is NULL");
     HIP_TRY(hipSetDevice(h->device), "set device");
+    int rc = fill_series(h, t0, steps + 1);
+    if (rc) return rc;
+    h->ghosts_ready = false;  // the forward's values table is overwritten
     const hlb::Layout L = h->layout();
     const hlb::Ghosts G = h->ghosts();
     HIP_TRY(hlb::launch_state(L, h->tape[0], const_cast<void*>(checkpoint), h->perm, 1, h->stream),
             "checkpoint restore");
     for (int64_t m = 0; m < steps; ++m) {
-        HIP_TRY(hlb::launch_ghost_fill(L, G, h->tape[m], t0 + m, h->stream), "recompute ghosts");
-        HIP_TRY(hlb::launch_stream_collide(L, h->tape[m], h->tape[m + 1], h->omega, h->alpha,
-                                           h->xcd_group, h->stream),
+        if (m == 0 || !hlb::ghosts_fused())
+            HIP_TRY(hlb::launch_ghost_fill(L, G, h->tape[m], t0 + m, h->stream), "recompute ghosts");
+        HIP_TRY(hlb::launch_stream_collide(L, G, h->tape[m], h->tape[m + 1], h->omega, h->alpha,
+                                           h->xcd_group, t0 + m + 1, h->stream),
                 "recompute");
     }
     const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};

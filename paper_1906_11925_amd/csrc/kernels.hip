@@ -44,15 +44,6 @@ constexpr int kScBlock = HLB_SC_BLOCK;
 static_assert(kScBlock % kTile == 0, "block must hold whole tiles");
 
 template <class T>
-__device__ inline T ld_table(const T* p) {
-#if HLB_NT_TABLE
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-
-template <class T>
 __device__ inline void st_pop(T* p, T v) {
 #if HLB_NT_STORE
     __builtin_nontemporal_store(v, p);
@@ -61,11 +52,40 @@ __device__ inline void st_pop(T* p, T v) {
 #endif
 }
 
+// Incoming population of iolet link l (direction i) of a site whose stored
+// populations decode to vs, at time t (the definition the ghost-fill kernel applies).
+template <int Q>
+__device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const float (&vs)[Q],
+                                    int64_t t) {
+    using Lt = Lat<Q>;
+    const int k = G.iolet[l];
+    const double v = G.vals[(t - G.vals_t0) * G.n_iolets + k];
+    if (G.iolets[k].kind == 0) {
+        float drho, mx, my, mz;
+        moments<Q>(vs, drho, mx, my, mz);
+        const float ir = 1.0f / (1.0f + drho);
+        const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+        const float cu = (float)Lt::cx[i] * ux + (float)Lt::cy[i] * uy + (float)Lt::cz[i] * uz;
+        const float usq = ux * ux + uy * uy + uz * uz;
+        const float rk = (float)v, rk1 = (float)(v - 1.0);
+        return Lt::w[i] * (rk1 + rk * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+    }
+    return vs[opp(i)] + G.coef[l] * (float)v;
+}
+
+// With HLB_FUSE_GHOSTS, a site that owns iolet links also writes the incoming
+// populations of those links for the next step (time t_next) into dst's ghost
+// slots, from its freshly stored populations; the separate ghost fill is then
+// only needed for a state that did not come out of this kernel.
+#ifndef HLB_FUSE_GHOSTS
+#define HLB_FUSE_GHOSTS 1
+#endif
+
 template <int Q, int ST, bool SC, bool BRINK>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    const int32_t* __restrict__ tbl, int32_t n, int32_t xcd_group, float omega,
-    const float* __restrict__ alpha) {
+    Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha,
+    Ghosts G, int64_t t_next) {
     using C = Codec<Q, ST, SC>;
     // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
     // xcd_group = G > 0, every XCD takes G consecutive tiles-blocks of a window of
@@ -77,12 +97,12 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
         b = (b / w) * w + (b & 7) * xcd_group + (b >> 3) % xcd_group;
     }
     const int32_t s = b * kScBlock + (int32_t)threadIdx.x;
-    if (s >= n) return;
+    if ((s & ~(kTile - 1)) >= n) return;  // the wavefront's whole tile lies past the end
 
     // all table loads, then all population gathers, before any arithmetic
     int32_t j[Q];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) j[i] = ld_table(tbl + tix<Q - 1>(i - 1, s));
+    links_wave<Q, HLB_NT_TABLE != 0>(tb, s, j);
+    if (s >= n) return;
     float d[Q];
     d[0] = C::dec(0, src[tix<Q>(0, s)]);
 #pragma unroll
@@ -106,47 +126,68 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     }
     float deq[Q];
     eq_dev<Q>(drho, rho, ux, uy, uz, deq);
+    float vs[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const float v = d[i] - omega * (d[i] - deq[i]);
-        st_pop(dst + tix<Q>(i, s), C::enc(i, v));
+        const typename Store<ST>::T e = C::enc(i, d[i] - omega * (d[i] - deq[i]));
+        st_pop(dst + tix<Q>(i, s), e);
+        vs[i] = C::dec(i, e);
     }
+#if HLB_FUSE_GHOSTS
+    // ghost links of a site occupy consecutive slots in direction order
+    uint32_t mask = 0;
+    int32_t first = 0x7fffffff;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (j[i] >= n) {
+            mask |= 1u << i;
+            first = min(first, j[i]);
+        }
+    if (mask) {
+        int32_t slot = first;
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (mask & (1u << i)) {
+                dst[tix<Q>(i, slot)] = C::enc(i, ghost_value<Q>(G, slot - n, i, vs, t_next));
+                ++slot;
+            }
+    }
+#else
+    (void)vs;
+    (void)G;
+    (void)t_next;
+#endif
 }
 
 // ---------------------------------------------------------------------------
 // iolet ghost fill: the incoming population of every iolet link for this step
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_iolet_series(const DevIolet* __restrict__ iolets,
+                                                          const double* __restrict__ harm,
+                                                          int32_t n_iolets, int64_t t0,
+                                                          int64_t count, double* __restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count * n_iolets) return;
+    const int64_t m = e / n_iolets;
+    const int k = (int)(e % n_iolets);
+    vals[e] = iolet_value(iolets[k], harm, (double)(t0 + m));
+}
+
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __restrict__ A,
-                                                        Ghosts G, int32_t n, double t) {
+                                                        Ghosts G, int32_t n, int64_t t) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= G.count) return;
     const int32_t s = G.site[l];
     const int i = G.dir[l];
-    const DevIolet io = G.iolets[G.iolet[l]];
-    const double v = iolet_value(io, G.harm, t);
-    float g;
-    if (io.kind == 0) {
-        // equilibrium at the iolet density with the site's own (lagged) velocity
-        float d[Q];
+    // pressure: equilibrium at the iolet density with the site's own (lagged)
+    // velocity; velocity: Ladd moving-wall bounce-back
+    float vs[Q];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) d[k] = C::dec(k, A[tix<Q>(k, s)]);
-        float drho, mx, my, mz;
-        moments<Q>(d, drho, mx, my, mz);
-        const float ir = 1.0f / (1.0f + drho);
-        const float ux = mx * ir, uy = my * ir, uz = mz * ir;
-        const float cu = (float)Lt::cx[i] * ux + (float)Lt::cy[i] * uy + (float)Lt::cz[i] * uz;
-        const float usq = ux * ux + uy * uy + uz * uz;
-        const float rk = (float)v, rk1 = (float)(v - 1.0);
-        g = Lt::w[i] * (rk1 + rk * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-    } else {
-        // Ladd moving-wall bounce-back
-        const int o = opp(i);
-        g = C::dec(o, A[tix<Q>(o, s)]) + G.coef[l] * (float)v;
-    }
-    A[tix<Q>(i, n + (int32_t)l)] = C::enc(i, g);
+    for (int k = 0; k < Q; ++k) vs[k] = C::dec(k, A[tix<Q>(k, s)]);
+    A[tix<Q>(i, n + (int32_t)l)] = C::enc(i, ghost_value<Q>(G, l, i, vs, t));
 }
 
 // ---------------------------------------------------------------------------
@@ -154,13 +195,16 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_observables(
-    const typename Store<ST>::T* __restrict__ A, const int32_t* __restrict__ tbl, int32_t n,
+    const typename Store<ST>::T* __restrict__ A, Table tb, int32_t n,
     int32_t streamed, float omega, const int32_t* __restrict__ perm,
     const float* __restrict__ normal, float* __restrict__ p, float* __restrict__ u,
     float* __restrict__ wss) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if ((s & ~(kTile - 1)) >= n) return;
+    int32_t j[Q];
+    if (streamed) links_wave<Q, false>(tb, s, j);
     if (s >= n) return;
     float d[Q];
     d[0] = C::dec(0, A[tix<Q>(0, s)]);
@@ -168,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_observables(
     for (int i = 1; i < Q; ++i) {
         int dir = i;
         int32_t site = s;
-        if (streamed) link_src(i, tbl[tix<Q - 1>(i - 1, s)], dir, site);
+        if (streamed) link_src(i, j[i], dir, site);
         d[i] = C::dec(i, A[tix<Q>(dir, site)]);
     }
     float drho, mx, my, mz;
@@ -339,13 +383,14 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_ghost_fill<Tg::Q, Tg::ST, Tg::SC><<<blocks_for(G.count), kBlock, 0, s>>>(
-            static_cast<T*>(A), G, (int32_t)L.n, (double)t);
+            static_cast<T*>(A), G, (int32_t)L.n, t);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, float omega,
-                                 const float* alpha, int xcd_group, hipStream_t s) {
+hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* src, void* dst,
+                                 float omega, const float* alpha, int xcd_group, int64_t t_next,
+                                 hipStream_t s) {
     if (L.n == 0) return hipSuccess;
     const int64_t nb = (L.n + kScBlock - 1) / kScBlock;
     const int32_t per = xcd_group > 0 ? xcd_group : 0;
@@ -356,12 +401,12 @@ hipError_t launch_stream_collide(const Layout& L, const void* src, void* dst, fl
         using T = typename Store<Tg::ST>::T;
         if (alpha)
             k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true><<<(unsigned)grid, kScBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, per, omega,
-                alpha);
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, per, omega,
+                alpha, G, t_next);
         else
             k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false><<<(unsigned)grid, kScBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tbl, (int32_t)L.n, per, omega,
-                nullptr);
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, per, omega,
+                nullptr, G, t_next);
         return hipGetLastError();
     });
 }
@@ -374,7 +419,7 @@ hipError_t launch_observables(const Layout& L, const void* A, int streamed, floa
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         k_observables<Tg::Q, Tg::ST, Tg::SC><<<blocks_for(L.n), kBlock, 0, s>>>(
-            static_cast<const T*>(A), L.tbl, (int32_t)L.n, streamed, omega, perm, normal, p, u,
+            static_cast<const T*>(A), L.tb, (int32_t)L.n, streamed, omega, perm, normal, p, u,
             wss);
         return hipGetLastError();
     });
@@ -414,6 +459,16 @@ hipError_t launch_zero(const Layout& L, void* A, hipStream_t s) {
     if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     k_zero<<<(unsigned)nb, kBlock, 0, s>>>(static_cast<uint32_t*>(A), words);
+    return hipGetLastError();
+}
+
+bool ghosts_fused() { return HLB_FUSE_GHOSTS != 0; }
+
+hipError_t launch_iolet_series(const DevIolet* iolets, const double* harm, int32_t n_iolets,
+                               int64_t t0, int64_t count, double* vals, hipStream_t s) {
+    if (n_iolets == 0 || count <= 0) return hipSuccess;
+    k_iolet_series<<<blocks_for(count * n_iolets), kBlock, 0, s>>>(iolets, harm, n_iolets, t0,
+                                                                   count, vals);
     return hipGetLastError();
 }
 

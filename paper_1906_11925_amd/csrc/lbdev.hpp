@@ -44,6 +44,53 @@ __device__ inline void link_src(int i, int32_t j, int& dir, int32_t& site) {
     site = j & 0x7fffffff;
 }
 
+template <bool NT, class T>
+__device__ inline T ld_maybe_nt(const T* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+// Links j[1..Q-1] of site s (decoded form).  Wave form: all 64 lanes of the
+// wavefront call it for the sites of one tile (lane = s & 63), lanes past n
+// included, because the compact decoding exchanges the tile's source list
+// between lanes.
+template <int Q, bool NT>
+__device__ inline void links_wave(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+    if (tb.t16 == nullptr) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) j[i] = ld_maybe_nt<NT>(tb.t32 + tix<Q - 1>(i - 1, s));
+        return;
+    }
+    const int32_t T = s >> kTileShift;
+    const int32_t off = tb.toff[T];
+    const int32_t cnt = tb.toff[T + 1] - off;
+    const int lane = s & (kTile - 1);
+    const int32_t e0 = lane < cnt ? tb.tlist[off + lane] : 0;
+    const int32_t e1 = lane + kTile < cnt ? tb.tlist[off + kTile + lane] : 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const uint32_t c = ld_maybe_nt<NT>(tb.t16 + tix<Q - 1>(i - 1, s));
+        const int slot = (int)((c >> kTileShift) & 0x1ffu);
+        const int32_t a = __shfl(e0, slot & (kTile - 1), kTile);
+        const int32_t b = __shfl(e1, slot & (kTile - 1), kTile);
+        const int32_t tile = slot < kTile ? a : b;
+        j[i] = (c & 0x8000u) ? (s | (int32_t)0x80000000u)
+                             : ((tile << kTileShift) | (int32_t)(c & (kTile - 1)));
+    }
+}
+
+// One link of an arbitrary site (no lane exchange).
+template <int Q>
+__device__ inline int32_t link_one(const Table& tb, int32_t s, int i) {
+    if (tb.t16 == nullptr) return tb.t32[tix<Q - 1>(i - 1, s)];
+    const uint32_t c = tb.t16[tix<Q - 1>(i - 1, s)];
+    if (c & 0x8000u) return s | (int32_t)0x80000000u;
+    const int32_t tile = tb.tlist[tb.toff[s >> kTileShift] + (int)((c >> kTileShift) & 0x1ffu)];
+    return (tile << kTileShift) | (int32_t)(c & (kTile - 1));
+}
+
 // moments of FP32 deviations: drho = sum d, m = sum c d (constant-folded per lattice)
 template <int Q>
 __device__ inline void moments(const float (&d)[Q], float& drho, float& mx, float& my, float& mz) {

@@ -48,7 +48,7 @@ class DescT(ctypes.Structure):
 class InfoT(ctypes.Structure):
     _fields_ = [("n_sites", c_int64), ("n_ghosts", c_int64), ("pitch", c_int64),
                 ("time", c_int64), ("lattice", c_int32), ("storage", c_int32),
-                ("bytes_per_update", c_int64), ("device_bytes", c_int64)]
+                ("bytes_per_update", c_double), ("device_bytes", c_int64)]
 
 
 class ObjectiveT(ctypes.Structure):

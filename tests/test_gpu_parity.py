@@ -383,3 +383,22 @@ def test_full_size_one_step(name):
     print(f"{name}: {o.n} sites", flush=True)
     assert np.abs(gpu - ref).max() < fp32_tol(15, 1e-3)
     assert np.abs(u - ou).max() < fp32_tol(15, 1e-3)
+
+
+def test_compact_table_matches_int32_table(monkeypatch):
+    """The 16-bit table (codes against per-tile source lists) decodes to the same
+    links as the int32 table: identical bits after 30 steps, observables too."""
+    _gpu()
+    g = wl.aneurysm(half=True)
+    runs = []
+    for mode in ("32", "16"):
+        monkeypatch.setenv("HEMELB_TABLE", mode)
+        lb = LB.from_geometry(g, storage="f16")
+        lb.step(30)
+        runs.append((lb.get_state()[0], lb.observables(), lb.info()["bytes_per_update"]))
+        lb.close()
+    assert torch.equal(runs[0][0], runs[1][0])
+    for x, y in zip(runs[0][1], runs[1][1]):
+        assert torch.equal(x, y)
+    assert runs[0][2] == 2 * 15 * 2 + 4 * 14
+    assert runs[1][2] < 2 * 15 * 2 + 2 * 14 + 4
