@@ -34,13 +34,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_run(lb, steps, warmup):
+def timed_run(lb, steps, warmup, obs_every=0):
     import torch
     lb.step(warmup)
     lb.sync()
     torch.cuda.synchronize()
+    obs = lb.observables() if obs_every > 0 else None  # outputs allocated before timing
     t0 = time.perf_counter()
-    lb.step(steps)
+    if obs_every > 0:
+        done = 0
+        while done < steps:
+            k = min(obs_every, steps - done)
+            lb.step(k)
+            done += k
+            if done % obs_every == 0:
+                lb.observables_into(*obs)
+    else:
+        lb.step(steps)
     lb.sync()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
@@ -67,6 +77,35 @@ def traffic_for(workload, storage):
     if not entry or rec.get("kernel_sha") != kernel_sha():
         return None
     return entry.get("bytes_per_launch")
+
+
+def pipe_errors(steps=2000):
+    """Error of each storage form against the FP64 oracle on the straight pipe
+    (13,312 sites, D3Q15, tau 0.8, pressure iolets) after `steps` steps:
+    max_s |x - x_ref| / max_s |x_ref| for velocity, pressure deviation and WSS."""
+    import numpy as np
+    import workloads as wl
+    from oracle.lbgk import LBGK
+    from paper_1906_11925_amd import LB
+    g = wl.pipe()
+    o = LBGK(g, 15)
+    _, f = o.run(o.rest_state(), 0, steps)
+    op, ou, _, ow = o.observables(f)
+    ref = {"u": ou.T, "p": op - 1.0 / 3.0, "wss": ow}
+
+    def rel(a, b):
+        if a.ndim == 2:
+            return float(np.sqrt(((a - b) ** 2).sum(1)).max() / np.sqrt((b ** 2).sum(1)).max())
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    out = {}
+    for st in ("f32", "f16", "bf16"):
+        lb = LB.from_geometry(g, storage=st)
+        lb.step(steps)
+        p, u, w = (x.cpu().numpy().astype(np.float64) for x in lb.observables())
+        out[st] = {"e_u": rel(u, ref["u"]), "e_p": rel(p, ref["p"]), "e_wss": rel(w, ref["wss"])}
+        lb.close()
+    return out
 
 
 def cpu_baseline(geom, lattice, nsteps):
@@ -149,6 +188,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps for cpu_baseline (0: skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and adjoint runs")
+    ap.add_argument("--obs-every", type=int, default=0,
+                    help="also compute velocity/pressure/WSS every k steps inside the timed run")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed stream+collide steps (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -195,7 +236,7 @@ def main():
         return
 
     log(f"[bench] timing {args.storage}: warmup {args.warmup}, steps {args.steps}")
-    dt = timed_run(lb, args.steps, args.warmup)
+    dt = timed_run(lb, args.steps, args.warmup, args.obs_every)
     glups = n * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
     avg_ms = kernel_avg_ms(lb, args.steps)
@@ -237,6 +278,20 @@ def main():
                          "speedup_vs_" + args.storage: dt / d}
             log(f"[bench] {st}: {extra[st]['GLUPS']:.2f} GLUPS")
             x.close()
+        if args.lattice == 15:
+            # the paper's lattice on the same workload
+            for st in ("f32", "f16"):
+                x = LB.from_geometry(geom, lattice=19, storage=st)
+                d = timed_run(x, args.steps, args.warmup, args.obs_every)
+                km = kernel_avg_ms(x, args.steps)
+                xb = x.info()["bytes_per_update"]
+                extra["d3q19_" + st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
+                                        "bytes_per_update": xb,
+                                        "achieved_GBs": xb * n / (km * 1e-3) / 1e9}
+                log(f"[bench] D3Q19 {st}: {extra['d3q19_' + st]['GLUPS']:.2f} GLUPS")
+                x.close()
+        log("[bench] storage errors vs oracle (pipe, 2000 steps)")
+        extra["errors_vs_oracle_pipe2000"] = pipe_errors()
         log("[bench] adjoint workload")
         extra["adjoint"] = adjoint_run()
         log(f"[bench] adjoint: {extra['adjoint']['adjoint_GLUPS']:.3f} GLUPS (reverse incl. recompute)")

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "lattice.hpp"
 #include "lbdev.hpp"
@@ -81,28 +83,13 @@ __device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const flo
 #define HLB_FUSE_GHOSTS 1
 #endif
 
+// Pull, collide and store one site whose links are decoded in j.
 template <int Q, int ST, bool SC, bool BRINK>
-__global__ __launch_bounds__(kScBlock) void k_stream_collide(
-    const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha,
-    Ghosts G, int64_t t_next) {
+__device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
+                                   typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
+                                   const float* __restrict__ alpha, const Ghosts& G,
+                                   int64_t t_next, int32_t s, const int32_t (&j)[Q]) {
     using C = Codec<Q, ST, SC>;
-    // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
-    // xcd_group = G > 0, every XCD takes G consecutive tiles-blocks of a window of
-    // 8G blocks, so neighbouring sites share an L2 while all XCDs still sweep the
-    // Morton order together (and share the last-level cache).
-    int32_t b = blockIdx.x;
-    if (xcd_group > 0) {
-        const int32_t w = 8 * xcd_group;
-        b = (b / w) * w + (b & 7) * xcd_group + (b >> 3) % xcd_group;
-    }
-    const int32_t s = b * kScBlock + (int32_t)threadIdx.x;
-    if ((s & ~(kTile - 1)) >= n) return;  // the wavefront's whole tile lies past the end
-
-    // all table loads, then all population gathers, before any arithmetic
-    int32_t j[Q];
-    links_wave<Q, HLB_NT_TABLE != 0>(tb, s, j);
-    if (s >= n) return;
     float d[Q];
     d[0] = C::dec(0, src[tix<Q>(0, s)]);
 #pragma unroll
@@ -156,6 +143,60 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     (void)vs;
     (void)G;
     (void)t_next;
+#endif
+}
+
+// Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
+// xcd_group = G > 0, every XCD takes G consecutive blocks of a window of 8G
+// blocks, so neighbouring sites share an L2 while all XCDs still sweep the
+// Morton order together (and share the last-level cache).
+__device__ inline int32_t xcd_block(int32_t b, int32_t xcd_group) {
+    if (xcd_group > 0) {
+        const int32_t w = 8 * xcd_group;
+        b = (b / w) * w + (b & 7) * xcd_group + (b >> 3) % xcd_group;
+    }
+    return b;
+}
+
+// HLB_PERSIST: a fixed grid whose wavefronts walk the tiles (stride = number of
+// wavefronts), loading the next tile's link codes before gathering the current one.
+#ifndef HLB_PERSIST
+#define HLB_PERSIST 0
+#endif
+
+template <int Q, int ST, bool SC, bool BRINK>
+__global__ __launch_bounds__(kScBlock) void k_stream_collide(
+    const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
+    Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha,
+    Ghosts G, int64_t t_next) {
+#if HLB_PERSIST
+    constexpr int kWaves = kScBlock / kTile;
+    const int32_t ntiles = (n + kTile - 1) >> kTileShift;
+    const int32_t stride = (int32_t)gridDim.x * kWaves;
+    const int32_t lane = (int32_t)(threadIdx.x & (kTile - 1));
+    int32_t T = xcd_block((int32_t)blockIdx.x, xcd_group) * kWaves + (int32_t)(threadIdx.x >> kTileShift);
+    if (T >= ntiles) return;
+    uint32_t c[Q];
+    int32_t e0, e1;
+    load_codes<Q, HLB_NT_TABLE != 0>(tb, T * kTile + lane, c, e0, e1);
+    for (;;) {
+        const int32_t s = T * kTile + lane;
+        int32_t j[Q];
+        decode_codes<Q>(tb, s, c, e0, e1, j);
+        const int32_t Tn = T + stride;
+        if (Tn < ntiles) load_codes<Q, HLB_NT_TABLE != 0>(tb, Tn * kTile + lane, c, e0, e1);
+        if (s < n) site_update<Q, ST, SC, BRINK>(src, dst, n, omega, alpha, G, t_next, s, j);
+        if (Tn >= ntiles) break;
+        T = Tn;
+    }
+#else
+    const int32_t s = xcd_block((int32_t)blockIdx.x, xcd_group) * kScBlock + (int32_t)threadIdx.x;
+    if ((s & ~(kTile - 1)) >= n) return;  // the wavefront's whole tile lies past the end
+    // all table loads, then all population gathers, before any arithmetic
+    int32_t j[Q];
+    links_wave<Q, HLB_NT_TABLE != 0>(tb, s, j);
+    if (s >= n) return;
+    site_update<Q, ST, SC, BRINK>(src, dst, n, omega, alpha, G, t_next, s, j);
 #endif
 }
 
@@ -392,7 +433,19 @@ hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* s
                                  float omega, const float* alpha, int xcd_group, int64_t t_next,
                                  hipStream_t s) {
     if (L.n == 0) return hipSuccess;
-    const int64_t nb = (L.n + kScBlock - 1) / kScBlock;
+    int64_t nb = (L.n + kScBlock - 1) / kScBlock;
+#if HLB_PERSIST
+    // enough resident wavefronts to fill every CU, no more than one tile each
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu <= 0)
+            ncu = 256;
+    }
+    nb = std::min<int64_t>(nb, (int64_t)ncu * HLB_PERSIST);
+#endif
     const int32_t per = xcd_group > 0 ? xcd_group : 0;
     int64_t grid = nb;
     if (per > 0) grid = ((nb + 8 * per - 1) / (8 * per)) * (8 * per);

@@ -55,30 +55,52 @@ __device__ inline T ld_maybe_nt(const T* p) {
 // Links j[1..Q-1] of site s (decoded form).  Wave form: all 64 lanes of the
 // wavefront call it for the sites of one tile (lane = s & 63), lanes past n
 // included, because the compact decoding exchanges the tile's source list
-// between lanes.
+// between lanes.  Split into the loads (load_codes) and the decoding
+// (decode_codes) so that a caller can issue the loads of the next tile early.
 template <int Q, bool NT>
-__device__ inline void links_wave(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+__device__ inline void load_codes(const Table& tb, int32_t s, uint32_t (&c)[Q], int32_t& e0,
+                                  int32_t& e1) {
     if (tb.t16 == nullptr) {
 #pragma unroll
-        for (int i = 1; i < Q; ++i) j[i] = ld_maybe_nt<NT>(tb.t32 + tix<Q - 1>(i - 1, s));
+        for (int i = 1; i < Q; ++i) c[i] = (uint32_t)ld_maybe_nt<NT>(tb.t32 + tix<Q - 1>(i - 1, s));
+        e0 = e1 = 0;
         return;
     }
     const int32_t T = s >> kTileShift;
     const int32_t off = tb.toff[T];
     const int32_t cnt = tb.toff[T + 1] - off;
     const int lane = s & (kTile - 1);
-    const int32_t e0 = lane < cnt ? tb.tlist[off + lane] : 0;
-    const int32_t e1 = lane + kTile < cnt ? tb.tlist[off + kTile + lane] : 0;
+    e0 = lane < cnt ? tb.tlist[off + lane] : 0;
+    e1 = lane + kTile < cnt ? tb.tlist[off + kTile + lane] : 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) c[i] = ld_maybe_nt<NT>(tb.t16 + tix<Q - 1>(i - 1, s));
+}
+
+template <int Q>
+__device__ inline void decode_codes(const Table& tb, int32_t s, const uint32_t (&c)[Q], int32_t e0,
+                                    int32_t e1, int32_t (&j)[Q]) {
+    if (tb.t16 == nullptr) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) j[i] = (int32_t)c[i];
+        return;
+    }
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const uint32_t c = ld_maybe_nt<NT>(tb.t16 + tix<Q - 1>(i - 1, s));
-        const int slot = (int)((c >> kTileShift) & 0x1ffu);
+        const int slot = (int)((c[i] >> kTileShift) & 0x1ffu);
         const int32_t a = __shfl(e0, slot & (kTile - 1), kTile);
         const int32_t b = __shfl(e1, slot & (kTile - 1), kTile);
         const int32_t tile = slot < kTile ? a : b;
-        j[i] = (c & 0x8000u) ? (s | (int32_t)0x80000000u)
-                             : ((tile << kTileShift) | (int32_t)(c & (kTile - 1)));
+        j[i] = (c[i] & 0x8000u) ? (s | (int32_t)0x80000000u)
+                                : ((tile << kTileShift) | (int32_t)(c[i] & (kTile - 1)));
     }
+}
+
+template <int Q, bool NT>
+__device__ inline void links_wave(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+    uint32_t c[Q];
+    int32_t e0, e1;
+    load_codes<Q, NT>(tb, s, c, e0, e1);
+    decode_codes<Q>(tb, s, c, e0, e1, j);
 }
 
 // One link of an arbitrary site (no lane exchange).

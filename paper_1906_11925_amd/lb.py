@@ -154,6 +154,11 @@ class LB:
                                                ctypes.c_void_p(w.data_ptr())))
         return p, u, w
 
+    def observables_into(self, p, u, w):
+        """Write the observables into existing float32 CUDA tensors (any may be None)."""
+        ptr = lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None  # noqa: E731
+        L.check(self.lib.hemelb_lb_observables(self.h, ptr(p), ptr(u), ptr(w)))
+
     def totals(self):
         out = (ctypes.c_double * 4)()
         L.check(self.lib.hemelb_lb_totals(self.h, out))
