@@ -39,16 +39,25 @@ from .links import Links, FLUID_LINK, WALL_LINK, IOLET_LINK
 
 
 class LBGK:
-    def __init__(self, geom, q=15, tau=None, alpha=None):
+    """The step over all sites, or with ``sites`` over a sample of them: the
+    sampled form reads a full state A [q, N] and returns f and A' only at the
+    sampled sites (for workloads too large to step whole on the CPU)."""
+
+    def __init__(self, geom, q=15, tau=None, alpha=None, sites=None):
         self.geom = geom
         self.lat = _lattice.get(q)
         self.q = self.lat.q
-        self.links = Links(geom, self.lat)
+        self.links = Links(geom, self.lat, sites)
         self.n = self.links.n
+        self.sites = None if sites is None else np.asarray(sites)
         self.tau = float(geom.tau if tau is None else tau)
         self.omega = 0.0 if math.isinf(self.tau) else 1.0 / self.tau
         self.alpha = None if alpha is None else np.asarray(alpha, dtype=np.float64)
         self.W = geom.site_weight()
+        if self.sites is not None:
+            self.W = self.W[self.sites]
+            if self.alpha is not None:
+                self.alpha = self.alpha[self.sites]
         self.iolets = list(geom.iolets)
         # per direction: iolet link masks, grouped by iolet
         self._io = []
@@ -80,19 +89,20 @@ class LBGK:
     def stream(self, A, t):
         """Pre-collision populations f of the step that starts at time t."""
         lat, L = self.lat, self.links
-        f = np.empty_like(A)
-        f[0] = A[0]
+        own = A if self.sites is None else A[:, self.sites]  # the sites' own stored populations
+        f = np.empty((self.q, self.n))
+        f[0] = own[0]
         u_own = None
         for i in range(1, self.q):
             fl = self._fluid[i]
             f[i, fl] = A[i, L.src[i, fl]]
             wl = self._wall[i]
-            f[i, wl] = A[lat.opp[i], wl]
+            f[i, wl] = own[lat.opp[i], wl]
             for k, sel in self._io[i]:
                 io = self.iolets[k]
                 if io.kind == "pressure":
                     if u_own is None:
-                        u_own = self.moments(A)[2]
+                        u_own = self.moments(own)[2]
                     rho_k = io.value(t)
                     us = u_own[:, sel]
                     cu = lat.cf[i] @ us
@@ -101,7 +111,7 @@ class LBGK:
                 elif io.kind == "velocity":
                     U = io.value(t)
                     ub = U * self.W[sel][None, :] * np.asarray(io.direction, dtype=np.float64)[:, None]
-                    f[i, sel] = A[lat.opp[i], sel] + 2.0 * lat.w[i] * (lat.cf[i] @ ub) / _lattice.CS2
+                    f[i, sel] = own[lat.opp[i], sel] + 2.0 * lat.w[i] * (lat.cf[i] @ ub) / _lattice.CS2
                 else:
                     raise ValueError(io.kind)
         return f

@@ -18,19 +18,26 @@ FLUID_LINK, WALL_LINK, IOLET_LINK = 0, 1, 2
 
 
 class Links:
-    def __init__(self, geom, lat):
+    """Links of every site, or with ``sites`` (indices into geom.coords) of those
+    sites only; ``src`` always indexes the full site list."""
+
+    def __init__(self, geom, lat, sites=None):
         X, Y, Z = geom.shape
-        coords = geom.coords.astype(np.int64)
-        n = coords.shape[0]
-        keys = (coords[:, 0] * Y + coords[:, 1]) * Z + coords[:, 2]
+        all_coords = geom.coords.astype(np.int64)
+        keys = (all_coords[:, 0] * Y + all_coords[:, 1]) * Z + all_coords[:, 2]
         order = np.argsort(keys, kind="stable")
         skeys = keys[order]
+        if sites is None:
+            coords = all_coords
+        else:
+            coords = all_coords[np.asarray(sites)]
+        n = coords.shape[0]
         q = lat.q
         self.n, self.q = n, q
         self.kind = np.zeros((q, n), dtype=np.int8)
         self.src = np.full((q, n), -1, dtype=np.int64)
         self.iolet = np.full((q, n), -1, dtype=np.int64)
-        self.src[0] = np.arange(n)
+        self.src[0] = np.arange(n) if sites is None else np.asarray(sites)
         for i in range(1, q):
             up = coords - lat.c[i]
             for a in range(3):

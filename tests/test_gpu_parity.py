@@ -385,6 +385,33 @@ def test_full_size_one_step(name):
     assert np.abs(u - ou).max() < fp32_tol(15, 1e-3)
 
 
+@pytest.fixture(scope="module")
+def tree2048():
+    return wl.config_geometry("tree2048")
+
+
+@pytest.mark.parametrize("q", [15, 19])
+def test_tree2048_one_step_sampled(tree2048, q):
+    """The largest workload (seeded Murray tree in a 2048^3 box, 53,020,072
+    sites): one step from a random state on the GPU, compared with the oracle's
+    sampled step at 20,000 random sites (and all their populations)."""
+    _gpu()
+    g = tree2048
+    n = g.n_sites
+    print(f"tree2048 D3Q{q}: {n} sites", flush=True)
+    d = wl.random_deviations(q, n, 17, 1e-3).astype(np.float32)
+    lb = LB.from_geometry(g, lattice=q)
+    lb.set_deviations(torch.from_numpy(d), t=11)
+    lb.step(1)
+    sites = np.sort(np.random.default_rng(5).choice(n, 20000, replace=False))
+    gpu = lb.get_deviations()[:, torch.from_numpy(sites).cuda()].cpu().numpy().astype(np.float64)
+    lb.close()
+    o = LBGK(g, q, sites=sites)
+    A, _ = o.step(o.lat.w[:, None] + d.astype(np.float64), 11)
+    ref = A - o.lat.w[:, None]
+    assert np.abs(gpu - ref).max() < fp32_tol(q, 1e-3)
+
+
 def test_compact_table_matches_int32_table(monkeypatch):
     """The 16-bit table (codes against per-tile source lists) decodes to the same
     links as the int32 table: identical bits after 30 steps, observables too."""

@@ -184,3 +184,18 @@ def test_tree_small_links_consistent():
         assert np.array_equal(L.src[o.lat.opp[i], L.src[i, fl]], fl)
     kinds = set(np.unique(L.iolet[L.kind == IOLET_LINK]).tolist())
     assert kinds == {0, 1}
+
+
+def test_sampled_step_equals_full_step():
+    """The oracle's sampled form (links and step at chosen sites only, reading the
+    full state) reproduces the full step at those sites exactly."""
+    g = wl.aneurysm(half=True)
+    full = LBGK(g, 15)
+    sites = np.sort(np.random.default_rng(0).choice(full.n, 700, replace=False))
+    alpha = np.random.default_rng(1).uniform(0, 0.01, full.n)
+    full_a = LBGK(g, 15, alpha=alpha)
+    samp = LBGK(g, 15, alpha=alpha, sites=sites)
+    A = full.rest_state() + wl.random_deviations(15, full.n, 3, 1e-3)
+    An, f = full_a.step(A, 5)
+    As, fs = samp.step(A, 5)
+    assert np.array_equal(As, An[:, sites]) and np.array_equal(fs, f[:, sites])
