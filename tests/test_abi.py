@@ -129,3 +129,20 @@ def test_null_handle_calls():
     assert lib.hemelb_lb_destroy(None) == L.HEMELB_EINVAL
     out = (ctypes.c_double * 4)()
     assert lib.hemelb_lb_totals(None, out) == L.HEMELB_EINVAL
+
+
+def test_reject_too_many_sites():
+    """N >= 2^30 is rejected on the host before anything is allocated."""
+    nbr = np.zeros((1, 15), dtype=np.int32)
+    d = _desc(nbr)
+    d.n_sites = 1 << 30
+    rc, msg = _create(d)
+    assert rc == L.HEMELB_EINVAL and "2^30" in msg
+
+
+def test_reject_bad_objective_and_order():
+    lib = L.load()
+    # objective calls on a NULL handle, adjoint calls out of order are host-side errors
+    assert lib.hemelb_lb_set_objective(None, None) == L.HEMELB_EINVAL
+    assert lib.hemelb_lb_adjoint_begin(None, 4) == L.HEMELB_EINVAL
+    assert lib.hemelb_lb_adjoint_grads(None, None, None) == L.HEMELB_EINVAL

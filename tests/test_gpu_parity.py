@@ -429,3 +429,65 @@ def test_compact_table_matches_int32_table(monkeypatch):
         assert torch.equal(x, y)
     assert runs[0][2] == 2 * 15 * 2 + 4 * 14
     assert runs[1][2] < 2 * 15 * 2 + 2 * 14 + 4
+
+
+def _lattice_box(shape, fluid_pts, iolet_pts=(), periodic=(False, False, False), tau=0.7,
+                 iolets=()):
+    lab = np.zeros(tuple(a + 2 for a in shape), dtype=np.uint8)
+    for p in fluid_pts:
+        lab[p[0] + 1, p[1] + 1, p[2] + 1] = 1
+    for p, k in iolet_pts:
+        lab[p[0] + 1, p[1] + 1, p[2] + 1] = 2 + k
+    return Geometry("edge", tuple(shape), lab, periodic=periodic, iolets=list(iolets), tau=tau)
+
+
+@pytest.mark.parametrize("count", [1, 63, 65, 127])
+def test_ragged_site_counts(count):
+    """Site counts that do not fill the last 64-site tile (and a single site)."""
+    _gpu()
+    rng = np.random.default_rng(count)
+    pts = set()
+    while len(pts) < count:
+        pts.add(tuple(int(v) for v in rng.integers(0, 9, 3)))
+    g = _lattice_box((9, 9, 9), sorted(pts), tau=0.65)
+    assert g.n_sites == count
+    for q in (15, 19):
+        gpu, ref, (p, u, w), (op, ou, ow), _ = _one_step_case(g, q, "f32", seed=count)
+        assert np.abs(gpu - ref).max() < fp32_tol(q, 1e-3)
+        assert np.abs(w - ow).max() < fp32_tol(q, 1e-3)
+
+
+def test_isolated_site_is_pure_bounce_back():
+    """A single fluid site enclosed by walls: every population bounces back, so
+    after two steps with tau = infinity the state returns exactly."""
+    _gpu()
+    g = _lattice_box((3, 3, 3), [(1, 1, 1)], tau=math.inf)
+    d = quantize(wl.random_deviations(15, 1, 2, 1e-2), 15, "f32")
+    lb = LB.from_geometry(g, tau=math.inf)
+    lb.set_deviations(torch.from_numpy(d))
+    lb.step(1)
+    once = _dev(lb)
+    o = LBGK(g, 15)
+    assert np.array_equal(once, d[o.lat.opp])
+    lb.step(1)
+    assert np.array_equal(_dev(lb), d)
+
+
+def test_site_with_only_iolet_links():
+    """A single site whose every upstream point lies past a pressure iolet."""
+    _gpu()
+    shape = (3, 3, 3)
+    around = [((x, y, z), 0) for x in range(-1, 4) for y in range(-1, 4) for z in range(-1, 4)
+              if (x, y, z) != (1, 1, 1) and max(abs(x - 1), abs(y - 1), abs(z - 1)) == 1]
+    g = _lattice_box(shape, [(1, 1, 1)], around, tau=0.8, iolets=[Iolet("pressure", mean=1.002)])
+    for q in (15, 19):
+        gpu, ref, _, _, _ = _one_step_case(g, q, "f32", seed=3)
+        assert np.abs(gpu - ref).max() < fp32_tol(q, 2e-3)
+
+
+@pytest.mark.parametrize("tau", [0.5000001, 0.51, 50.0, 1e6])
+def test_extreme_relaxation_times(tau):
+    _gpu()
+    g = wl.aneurysm(half=True)
+    gpu, ref, _, _, _ = _one_step_case(g, 15, "f32", seed=21, tau=tau)
+    assert np.abs(gpu - ref).max() < fp32_tol(15, 1e-3)
