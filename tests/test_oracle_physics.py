@@ -199,3 +199,29 @@ def test_sampled_step_equals_full_step():
     An, f = full_a.step(A, 5)
     As, fs = samp.step(A, 5)
     assert np.array_equal(As, An[:, sites]) and np.array_equal(fs, f[:, sites])
+
+
+def test_pulsatile_inlet_mass_over_a_period():
+    """Pulsatile Ladd inlet U(t) = U0 (1 + 0.5 sin(2 pi t / P)): the mass that
+    enters during one period equals P * U0 * sum of W_s over the inlet plane
+    (area-weighted parabolic profile), up to the rim sites whose links are
+    partly walls (a few percent here).  The sinusoid integrates to zero over
+    the period, so only the mean inlet speed survives."""
+    P, U0 = 100, 0.02
+    g = wl.pipe(X=12, Y=12, Z=16, r2=25.0, tau=0.8,
+                inlet_velocity=(U0, (0.0,), (0.5 * U0,), float(P)))
+    o = LBGK(g, 15)
+    A = o.rest_state()
+    A, _ = o.run(A, 0, P)
+    inlet = [(i, np.nonzero((o.links.kind[i] == IOLET_LINK) & (o.links.iolet[i] == 0))[0])
+             for i in range(1, o.q)]
+    injected = 0.0
+    for t in range(P, 2 * P):
+        An, f = o.step(A, t)
+        for i, sel in inlet:
+            injected += np.sum(f[i, sel] - A[o.lat.opp[i], sel])
+        A = An
+    W = g.site_weight()
+    plane = g.coords[:, 2] == 0
+    expected = P * U0 * np.sum(W[plane])
+    assert abs(injected / expected - 1.0) < 0.05
