@@ -21,6 +21,15 @@ uses boundary time t = n - 1 and maps A_{n-1} to A_n:
 4. LBGK collision (Section 2, collision): A'[i, s] = f_i - (f_i - f_i^eq(rho, u_b)) / tau,
    with the Brinkman-damped velocity u_b = (1 - alpha_s) u (alpha = 0 by default).
 
+Interpolated walls (the BFL wall boundary Section 3.B selects; Bouzidi,
+Firdaouss and Lallemand 2001, linear variant): with ``wall_q`` the wall of link
+i at site s lies at fraction q of the way from x_s to x_s - c_i, and with
+o = opp(i) (the population that travels into the wall)
+   q <  1/2:  f_i(s) = 2q A[o, s] + (1 - 2q) A[o, s'],  s' = x_s + c_i (the site o
+              pulls from); halfway bounce-back when s' is not a fluid site;
+   q >= 1/2:  f_i(s) = A[o, s] / (2q) + (2q - 1)/(2q) A[i, s].
+q = 1/2 gives halfway bounce-back in both branches.
+
 Observables after n steps come from the pre-collision f of step n: pressure
 p = rho / 3, velocity u, deviatoric stress
 sigma = -(1 - 1/(2 tau)) sum_i c_i c_i (f_i - f_i^eq(rho, u)), and at sites with
@@ -43,7 +52,7 @@ class LBGK:
     sampled form reads a full state A [q, N] and returns f and A' only at the
     sampled sites (for workloads too large to step whole on the CPU)."""
 
-    def __init__(self, geom, q=15, tau=None, alpha=None, sites=None):
+    def __init__(self, geom, q=15, tau=None, alpha=None, sites=None, wall_q=None):
         self.geom = geom
         self.lat = _lattice.get(q)
         self.q = self.lat.q
@@ -58,6 +67,10 @@ class LBGK:
             self.W = self.W[self.sites]
             if self.alpha is not None:
                 self.alpha = self.alpha[self.sites]
+        self.wall_q = None
+        if wall_q is not None:
+            wq = np.asarray(wall_q, dtype=np.float64)
+            self.wall_q = (wq if self.sites is None else wq[self.sites]).T  # [q, n]
         self.iolets = list(geom.iolets)
         # per direction: iolet link masks, grouped by iolet
         self._io = []
@@ -97,7 +110,16 @@ class LBGK:
             fl = self._fluid[i]
             f[i, fl] = A[i, L.src[i, fl]]
             wl = self._wall[i]
-            f[i, wl] = own[lat.opp[i], wl]
+            o = lat.opp[i]
+            f[i, wl] = own[o, wl]
+            if self.wall_q is not None:
+                q = self.wall_q[i, wl]
+                near = np.nonzero((q < 0.5) & (L.kind[o, wl] == FLUID_LINK))[0]
+                far = np.nonzero(q >= 0.5)[0]
+                qn, sn = q[near], wl[near]
+                f[i, sn] = 2.0 * qn * own[o, sn] + (1.0 - 2.0 * qn) * A[o, L.src[o, sn]]
+                qf, sf = q[far], wl[far]
+                f[i, sf] = own[o, sf] / (2.0 * qf) + (2.0 * qf - 1.0) / (2.0 * qf) * own[i, sf]
             for k, sel in self._io[i]:
                 io = self.iolets[k]
                 if io.kind == "pressure":

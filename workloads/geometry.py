@@ -68,6 +68,9 @@ class Geometry:
     # inlet velocity profile: (point on axis, unit axis, radius); None -> weight 1
     profile: tuple | None = None
     info: dict = field(default_factory=dict)
+    # continuous fluid predicate on float points [M, 3] (the one the labels sample
+    # at integer points); None for geometries without a curved wall description
+    inside: object = field(default=None, repr=False)
 
     _coords: np.ndarray | None = field(default=None, repr=False)
 
@@ -99,6 +102,37 @@ class Geometry:
         t = v @ a
         r2 = np.einsum("ij,ij->i", v, v) - t * t
         return np.maximum(0.0, 1.0 - r2 / (R * R))
+
+    def wall_fractions(self, dirs, iters=40):
+        """Wall position along every wall link, float64 [N, len(dirs)] (NaN where the
+        link is not a wall link): for fluid site x and lattice vector c (dirs[i])
+        whose point x - c is solid, the fraction q in (0, 1] of the segment from
+        x towards x - c at which the continuous wall crosses it (bisection of
+        ``inside``).  Interpolated (BFL) walls use it."""
+        if self.inside is None:
+            raise ValueError(f"{self.name} has no continuous wall description")
+        c = self.coords.astype(np.int64)
+        dirs = np.asarray(dirs, dtype=np.int64)
+        out = np.full((c.shape[0], len(dirs)), np.nan)
+        for i, d in enumerate(dirs):
+            if not d.any():
+                continue
+            up = c - d
+            lab = self.label_at(up)
+            wall = np.nonzero(lab == SOLID)[0]
+            if len(wall) == 0:
+                continue
+            x0 = c[wall].astype(np.float64)
+            step = -d.astype(np.float64)
+            lo = np.zeros(len(wall))
+            hi = np.ones(len(wall))
+            for _ in range(iters):
+                mid = 0.5 * (lo + hi)
+                ins = self.inside(x0 + mid[:, None] * step[None, :])
+                lo = np.where(ins, mid, lo)
+                hi = np.where(ins, hi, mid)
+            out[wall, i] = 0.5 * (lo + hi)
+        return out
 
     def label_at(self, pts: np.ndarray) -> np.ndarray:
         """Labels of integer points [M, 3]; periodic axes wrap, others must lie
@@ -157,8 +191,11 @@ def pipe(X=20, Y=20, Z=64, r2=64.0, rho_in=1.001, rho_out=1.0, tau=0.8, inlet_ve
         iolets[0] = Iolet("velocity", direction=(0.0, 0.0, 1.0), mean=mean, cos=tuple(cos),
                           sin=tuple(sin), period=period)
         profile = ((cx, cy, 0.0), (0.0, 0.0, 1.0), float(np.sqrt(r2)))
+    def inside(p):
+        return (p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 < r2
+
     return Geometry("pipe", shape, lab, iolets=iolets, tau=tau, profile=profile,
-                    info=dict(r2=r2, rho_in=rho_in, rho_out=rho_out))
+                    info=dict(r2=r2, rho_in=rho_in, rho_out=rho_out), inside=inside)
 
 
 # ----------------------------------------------------------------------------
@@ -209,8 +246,15 @@ def aneurysm(half=False, tau=0.6, u_mean=0.02, u_amp=0.01, period=4000.0):
     ]
     profile = ((cx - R, y0, zc), (0.0, 1.0, 0.0), r)
     dome_info = dict(centre=tuple(sc), radius=rs, arc_centre=(cx, y0, zc), R=R, r=r)
+
+    def inside(p):
+        rho = np.sqrt((p[:, 0] - cx) ** 2 + (p[:, 1] - y0) ** 2)
+        tube = ((rho - R) ** 2 + (p[:, 2] - zc) ** 2 < r * r) & (p[:, 1] >= y0)
+        dome = ((p[:, 0] - sc[0]) ** 2 + (p[:, 1] - sc[1]) ** 2 + (p[:, 2] - sc[2]) ** 2) < rs * rs
+        return tube | dome
+
     return Geometry("aneurysm_half" if half else "aneurysm", shape, lab, iolets=iolets,
-                    tau=tau, profile=profile, info=dome_info)
+                    tau=tau, profile=profile, info=dome_info, inside=inside)
 
 
 # ----------------------------------------------------------------------------
@@ -338,17 +382,23 @@ def tree(box=1024, r0=32.0, root=(512.0, 512.0, 16.0), generations=7, seed=3, ta
 # small analytic test geometries
 # ----------------------------------------------------------------------------
 
-def couette(H=8, Lx=4, Lz=4, U=0.01, tau=0.8):
+def couette(H=8, Lx=4, Lz=4, U=0.01, tau=0.8, wall_gap=0.5):
     """Plane Couette cell: periodic in x and z, fluid 0 <= y < H.  A resting
-    wall lies beyond y = 0 (bounce-back), a wall moving with velocity (U,0,0)
-    beyond y = H-1 (velocity iolet 0, direction +x, weight 1)."""
+    wall lies beyond y = 0, at y = -wall_gap (the continuous wall used by
+    interpolated walls; halfway bounce-back places it at -1/2), a wall moving
+    with velocity (U,0,0) beyond y = H-1 (velocity iolet 0, direction +x,
+    weight 1)."""
     shape = (Lx, H, Lz)
     lab = _empty(shape)
     lab[:, 1:H + 1, :] = FLUID
     lab[:, H + 1, :] = 2
+
+    def inside(p):
+        return p[:, 1] > -wall_gap
+
     return Geometry("couette", shape, lab, periodic=(True, False, True),
                     iolets=[Iolet("velocity", direction=(1.0, 0.0, 0.0), mean=U)], tau=tau,
-                    info=dict(H=H, U=U))
+                    info=dict(H=H, U=U, wall_gap=wall_gap), inside=inside)
 
 
 def channel(H=8, L=48, Lx=4, rho_in=1.001, rho_out=1.0, tau=0.6):
@@ -359,9 +409,12 @@ def channel(H=8, L=48, Lx=4, rho_in=1.001, rho_out=1.0, tau=0.6):
     lab[:, 1:H + 1, 1:L + 1] = FLUID
     lab[:, 1:H + 1, 0] = 2
     lab[:, 1:H + 1, L + 1] = 3
+    def inside(p):
+        return (p[:, 1] > -0.5) & (p[:, 1] < H - 0.5)
+
     return Geometry("channel", shape, lab, periodic=(True, False, False),
                     iolets=[Iolet("pressure", mean=rho_in), Iolet("pressure", mean=rho_out)],
-                    tau=tau, info=dict(H=H, L=L))
+                    tau=tau, info=dict(H=H, L=L), inside=inside)
 
 
 def closed_box(X=6, Y=5, Z=7, tau=0.7):
