@@ -12,7 +12,8 @@
  * One step, as this library computes it, for every fluid site s and lattice
  * direction i (upstream point y = x_s - c_i):
  *   f_i(s) = A[i][y]                                   y fluid
- *          = A[opp(i)][s]                              y wall (halfway bounce-back)
+ *          = A[opp(i)][s]                              y wall (halfway bounce-back;
+ *                                                      interpolated with wall_q)
  *          = f_i^eq(rho_k(t), u_s)                     y past pressure iolet k,
  *                                                      u_s = velocity of A[:][s]
  *          = A[opp(i)][s] + 6 w_i (c_i . e_k) U_k(t) W_s   y past velocity iolet k (Ladd)
@@ -117,6 +118,13 @@ typedef struct {
  *                (normalize(sum of c_i over wall links i))
  *   alpha        float [N] Brinkman damping in [0, 1], or NULL (0)
  *   stream       hipStream_t for all work of the handle, or NULL (default stream)
+ *   wall_q       float [N][lattice], or NULL for halfway bounce-back everywhere: for
+ *                every wall link (nbr[s][i] == HEMELB_LINK_WALL) the fraction q in
+ *                (0, 1] of the way from the site to its upstream point at which the
+ *                wall lies (other entries ignored).  Wall links then use the
+ *                interpolated bounce-back of Bouzidi, Firdaouss and Lallemand (the
+ *                BFL wall boundary of Section 3.B, linear variant); q is rounded to a
+ *                multiple of 2^-15.  Not supported by the adjoint calls.
  */
 typedef struct {
     int32_t lattice;
@@ -132,6 +140,7 @@ typedef struct {
     const float* wall_normal;
     const float* alpha;
     void* stream;
+    const float* wall_q;
 } hemelb_lb_desc_t;
 
 typedef struct {

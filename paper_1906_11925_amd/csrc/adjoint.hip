@@ -39,7 +39,7 @@ constexpr int kObjBlock = 1024;
 // ghosts, given its decoded links j
 template <int Q, int ST, bool SC>
 __device__ inline void gather_pre(const typename Store<ST>::T* __restrict__ A, int32_t s,
-                                  float (&d)[Q], int32_t (&j)[Q]) {
+                                  int32_t n, float (&d)[Q], int32_t (&j)[Q]) {
     using C = Codec<Q, ST, SC>;
     j[0] = s;
     d[0] = C::dec(0, A[tix<Q>(0, s)]);
@@ -47,9 +47,10 @@ __device__ inline void gather_pre(const typename Store<ST>::T* __restrict__ A, i
     for (int i = 1; i < Q; ++i) {
         int dir;
         int32_t site;
-        link_src(i, j[i], dir, site);
+        link_src(i, j[i], s, dir, site);
         d[i] = C::dec(i, A[tix<Q>(dir, site)]);
     }
+    apply_bfl<Q, ST, SC>(A, s, n, j, d);
 }
 
 // traction tangential to the wall, t = sigma n - (n.sigma n) n, with
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kObjBlock) void k_objective(
         int32_t j[Q];
 #pragma unroll
         for (int i = 1; i < Q; ++i) j[i] = link_one<Q>(tb, s, i);
-        gather_pre<Q, ST, SC>(A, s, d, j);
+        gather_pre<Q, ST, SC>(A, s, n, d, j);
         float drho, mx, my, mz;
         moments<Q>(d, drho, mx, my, mz);
         const float ir = 1.0f / (1.0f + drho);
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     int32_t j[Q];
     links_wave<Q, false>(tb, s, j);
     if (s >= n) return;
-    gather_pre<Q, ST, SC>(A, s, d, j);
+    gather_pre<Q, ST, SC>(A, s, n, d, j);
     float g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = gin[tix<Q>(i, s)];
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     for (int i = 1; i < Q; ++i) {
         int dir;
         int32_t site;
-        link_src(i, j[i], dir, site);
+        link_src(i, j[i], s, dir, site);
         gout[tix<Q>(dir, site)] = fh[i];
         // an iolet link: the population opp(i) of this site leaves the domain
         if (j[i] >= n) gout[tix<Q>(opp(i), s)] = 0.0f;

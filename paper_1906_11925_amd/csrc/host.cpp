@@ -81,6 +81,15 @@ HostLat host_lattice(int q) {
 
 inline int opp_dir(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// wall fraction q in (0, 1] -> multiple of 2^-15 in [1, 32767] (0 is reserved for
+// halfway bounce-back)
+inline uint32_t wall_code(float q) {
+    long k = lroundf(q * 32768.0f);
+    if (k < 1) k = 1;
+    if (k > 32767) k = 32767;
+    return (uint32_t)k;
+}
+
 inline uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
     v &= 0x1fffffull;
     v = (v | (v << 32)) & 0x1f00000000ffffull;
@@ -124,6 +133,7 @@ struct hemelb_lb {
 
     void* A[2] = {nullptr, nullptr};
     int cur = 0;  // A[cur] holds the current post-collision state
+    bool bfl = false;           // interpolated walls present
     int32_t* tbl = nullptr;     // int32 table (when the compact one does not apply)
     uint16_t* t16 = nullptr;    // compact table
     int32_t* toff = nullptr;
@@ -323,6 +333,15 @@ int validate(const hemelb_lb_desc_t* d) {
         for (int64_t s = 0; s < 3 * n; ++s)
             if (!std::isfinite(d->wall_normal[s]))
                 return fail(HEMELB_EINVAL, "wall_normal[%lld] not finite", (long long)(s / 3));
+    if (d->wall_q)
+        for (int64_t s = 0; s < n; ++s)
+            for (int i = 1; i < q; ++i)
+                if (nb[s * q + i] == HEMELB_LINK_WALL) {
+                    const float v = d->wall_q[s * q + i];
+                    if (!(v > 0.f && v <= 1.f))
+                        return fail(HEMELB_EINVAL, "wall_q[%lld][%d] = %g outside (0, 1]",
+                                    (long long)s, i, (double)v);
+                }
     return HEMELB_OK;
 }
 
@@ -514,6 +533,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     h->storage = d->storage;
     h->flags = d->flags;
     h->scaled = d->storage != HEMELB_STORE_F32 && !(d->flags & HEMELB_FLAG_NO_SCALE);
+    h->bfl = d->wall_q != nullptr;
     h->n = d->n_sites;
     h->tau = d->tau;
     h->omega = std::isinf(d->tau) ? 0.0f : (float)(1.0 / d->tau);
@@ -587,8 +607,9 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     if (h->ttiles == 0) h->ttiles = 1;
 
     // internal pull table [tile][q-1][64]: fluid -> Morton index of the upstream
-    // site; wall -> own index with bit 31 set (read the opposite direction of the
-    // same site); iolet -> ghost slot n + l
+    // site; wall -> bit 31 set (read the opposite direction of the same site) with
+    // the interpolated-wall fraction in units of 2^-15 in the low bits (0: halfway);
+    // iolet -> ghost slot n + l
     std::vector<int32_t> tbl((size_t)h->ttiles * (q - 1) * hlb::kTile, 0);
     {
         std::vector<int64_t> gbase(n + 1, 0);
@@ -603,7 +624,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
                 if (v >= 0)
                     e = (uint32_t)inv[v];
                 else if (v == HEMELB_LINK_WALL)
-                    e = (uint32_t)m | 0x80000000u;
+                    e = 0x80000000u | (d->wall_q ? wall_code(d->wall_q[s * q + i]) : 0u);
                 else
                     e = (uint32_t)(n + (g++));
                 const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
@@ -711,7 +732,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
                     const int32_t v = tbl[base + e];
                     uint16_t c;
                     if (v < 0) {
-                        c = 0x8000u;
+                        c = (uint16_t)(0x8000u | ((uint32_t)v & 0x7fffu));
                     } else {
                         const int32_t slot = (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
                                                                         v >> hlb::kTileShift) -
@@ -1071,6 +1092,8 @@ int hemelb_lb_objective_flux(hemelb_lb_t h, double* q) {
 int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (!h->obj_set) return fail(HEMELB_EORDER, "set an objective and run the forward first");
+    if (h->bfl)
+        return fail(HEMELB_EINVAL, "the adjoint covers halfway bounce-back walls only (no wall_q)");
     if (max_segment < 1) return fail(HEMELB_EINVAL, "max_segment must be >= 1");
     HIP_TRY(hipSetDevice(h->device), "set device");
     const size_t popbytes = (size_t)h->q * h->slots * h->elem();

@@ -96,9 +96,10 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
     for (int i = 1; i < Q; ++i) {
         int dir;
         int32_t site;
-        link_src(i, j[i], dir, site);
+        link_src(i, j[i], s, dir, site);
         d[i] = C::dec(i, src[tix<Q>(dir, site)]);
     }
+    apply_bfl<Q, ST, SC>(src, s, n, j, d);
 
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -253,9 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_observables(
     for (int i = 1; i < Q; ++i) {
         int dir = i;
         int32_t site = s;
-        if (streamed) link_src(i, j[i], dir, site);
+        if (streamed) link_src(i, j[i], s, dir, site);
         d[i] = C::dec(i, A[tix<Q>(dir, site)]);
     }
+    if (streamed) apply_bfl<Q, ST, SC>(A, s, n, j, d);
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
     const float rho = 1.0f + drho;

@@ -37,11 +37,40 @@ __device__ inline int64_t tix(int i, int32_t s) {
     return ((int64_t)(s >> kTileShift) * R + i) * kTile + (s & (kTile - 1));
 }
 
-// decode a table entry for direction i: (source direction, source site)
-__device__ inline void link_src(int i, int32_t j, int& dir, int32_t& site) {
+// decode a table entry j for direction i of site s: (source direction, source site).
+// A wall link (bit 31 set) reads the opposite population of the site itself; its
+// low 15 bits hold the interpolated-wall fraction (0: halfway bounce-back).
+__device__ inline void link_src(int i, int32_t j, int32_t s, int& dir, int32_t& site) {
     const bool wall = j < 0;
     dir = wall ? opp(i) : i;
-    site = j & 0x7fffffff;
+    site = wall ? s : j;
+}
+
+// Interpolated (BFL, linear) walls on gathered pre-collision deviations d: for a
+// wall link i with fraction q = code / 2^15 (o = opp(i), d[i] holding A[o][s]):
+//   q <  1/2: d_i = 2q A[o][s] + (1 - 2q) A[o][s + c_i]   (the value pulled for o,
+//             when link o is a fluid link; halfway bounce-back otherwise)
+//   q >= 1/2: d_i = A[o][s] / (2q) + (2q - 1)/(2q) A[i][s]
+// The weights sum to one, so the rule applies to deviations unchanged.
+template <int Q, int ST, bool SC>
+__device__ inline void apply_bfl(const typename Store<ST>::T* __restrict__ A, int32_t s, int32_t n,
+                                 const int32_t (&j)[Q], float (&d)[Q]) {
+    using C = Codec<Q, ST, SC>;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int32_t code = j[i] & 0x7fff;
+        if (j[i] < 0 && code != 0) {
+            const int o = opp(i);
+            const float q = (float)code * (1.0f / 32768.0f);
+            const float bb = d[i];
+            if (q < 0.5f) {
+                if (j[o] >= 0 && j[o] < n) d[i] = 2.0f * q * bb + (1.0f - 2.0f * q) * d[o];
+            } else {
+                const float own = C::dec(i, A[tix<Q>(i, s)]);
+                d[i] = bb / (2.0f * q) + (2.0f * q - 1.0f) / (2.0f * q) * own;
+            }
+        }
+    }
 }
 
 template <bool NT, class T>
@@ -90,7 +119,7 @@ __device__ inline void decode_codes(const Table& tb, int32_t s, const uint32_t (
         const int32_t a = __shfl(e0, slot & (kTile - 1), kTile);
         const int32_t b = __shfl(e1, slot & (kTile - 1), kTile);
         const int32_t tile = slot < kTile ? a : b;
-        j[i] = (c[i] & 0x8000u) ? (s | (int32_t)0x80000000u)
+        j[i] = (c[i] & 0x8000u) ? (int32_t)(0x80000000u | (c[i] & 0x7fffu))
                                 : ((tile << kTileShift) | (int32_t)(c[i] & (kTile - 1)));
     }
 }
@@ -108,7 +137,7 @@ template <int Q>
 __device__ inline int32_t link_one(const Table& tb, int32_t s, int i) {
     if (tb.t16 == nullptr) return tb.t32[tix<Q - 1>(i - 1, s)];
     const uint32_t c = tb.t16[tix<Q - 1>(i - 1, s)];
-    if (c & 0x8000u) return s | (int32_t)0x80000000u;
+    if (c & 0x8000u) return (int32_t)(0x80000000u | (c & 0x7fffu));
     const int32_t tile = tb.tlist[tb.toff[s >> kTileShift] + (int)((c >> kTileShift) & 0x1ffu)];
     return (tile << kTileShift) | (int32_t)(c & (kTile - 1));
 }

@@ -37,6 +37,17 @@ def links(labels, shape, periodic, lattice):
     return coords, nbr
 
 
+def lattice_vectors(lattice):
+    """Lattice vectors in the interface ordering (rest, then opposite pairs)."""
+    faces = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    second = ([(1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1)] if lattice == 15 else
+              [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)])
+    out = [(0, 0, 0)]
+    for v in faces + second:
+        out += [v, tuple(-a for a in v)]
+    return np.array(out, dtype=np.int64)
+
+
 def _torch():
     import torch
     return torch
@@ -46,7 +57,8 @@ class LB:
     """One simulation handle on the current GPU (see include/hemelb_lb.h)."""
 
     def __init__(self, nbr, tau, lattice=15, storage="f32", coords=None, iolets=(),
-                 site_weight=None, wall_normal=None, alpha=None, stream=None, scale=True):
+                 site_weight=None, wall_normal=None, alpha=None, stream=None, scale=True,
+                 wall_q=None):
         torch = _torch()
         self.lib = L.load()
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
@@ -87,9 +99,12 @@ class LB:
         d.tau = self.tau
         d.n_iolets = len(iolets)
         d.iolets = io_arr
+        if wall_q is not None:
+            wall_q = np.nan_to_num(np.asarray(wall_q, dtype=np.float32), nan=0.5)
         for name, arr, ct, dt in (("site_weight", site_weight, L.c_double, np.float64),
                                   ("wall_normal", wall_normal, L.c_float, np.float32),
-                                  ("alpha", alpha, L.c_float, np.float32)):
+                                  ("alpha", alpha, L.c_float, np.float32),
+                                  ("wall_q", wall_q, L.c_float, np.float32)):
             if arr is not None:
                 a = np.ascontiguousarray(arr, dtype=dt)
                 keep.append(a)
@@ -102,8 +117,13 @@ class LB:
         del keep
 
     @classmethod
-    def from_geometry(cls, geom, lattice=15, storage="f32", tau=None, alpha=None, **kw):
+    def from_geometry(cls, geom, lattice=15, storage="f32", tau=None, alpha=None, bfl=False,
+                      **kw):
+        """Handle for a workloads.Geometry; bfl=True places the walls where the
+        geometry's continuous surface cuts each wall link (interpolated walls)."""
         coords, nbr = links(geom.labels, geom.shape, geom.periodic, lattice)
+        if bfl:
+            kw["wall_q"] = geom.wall_fractions(lattice_vectors(lattice))
         return cls(nbr, geom.tau if tau is None else tau, lattice=lattice, storage=storage,
                    coords=coords, iolets=list(geom.iolets), site_weight=geom.site_weight(),
                    alpha=alpha, **kw)

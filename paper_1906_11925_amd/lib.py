@@ -42,7 +42,7 @@ class DescT(ctypes.Structure):
                 ("n_sites", c_int64), ("coords", P(c_int32)), ("nbr", P(c_int32)),
                 ("tau", c_double), ("n_iolets", c_int32), ("iolets", P(IoletT)),
                 ("site_weight", P(c_double)), ("wall_normal", P(c_float)),
-                ("alpha", P(c_float)), ("stream", c_void_p)]
+                ("alpha", P(c_float)), ("stream", c_void_p), ("wall_q", P(c_float))]
 
 
 class InfoT(ctypes.Structure):
