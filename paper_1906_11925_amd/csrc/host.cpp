@@ -250,7 +250,7 @@ int dev_upload(hemelb_lb* h, T** p, const std::vector<T>& v, const char* what) {
 
 void release(hemelb_lb* h) {
     if (!h) return;
-    if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
                     h->t16,       h->toff,      h->tlist,
                     h->g_iolet,   h->g_coef,    h->d_iolets,   h->d_harm,    h->perm,
