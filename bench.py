@@ -250,7 +250,7 @@ def main():
              "populations_only_GBs": (bpu - 4 * (args.lattice - 1)) * n / (avg_ms * 1e-3) / 1e9}
     # practical ceiling: plain device copy of the same byte count
     from paper_1906_11925_amd import copy_probe
-    nbytes = (bpu * n // 2 // 16) * 16
+    nbytes = int(bpu * n // 2 // 16) * 16
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
