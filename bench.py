@@ -34,13 +34,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_run(lb, steps, warmup, obs_every=0):
+def timed_run(lb, steps, warmup, obs_every=0, events=None):
+    """Wall time of `steps` steps; with events=(start, end) (HIP events on the
+    library's stream, which is torch's current stream) also brackets them on
+    the GPU."""
     import torch
     lb.step(warmup)
     lb.sync()
     torch.cuda.synchronize()
     obs = lb.observables() if obs_every > 0 else None  # outputs allocated before timing
     t0 = time.perf_counter()
+    if events:
+        events[0].record()
     if obs_every > 0:
         done = 0
         while done < steps:
@@ -51,14 +56,26 @@ def timed_run(lb, steps, warmup, obs_every=0):
                 lb.observables_into(*obs)
     else:
         lb.step(steps)
+    if events:
+        events[1].record()
     lb.sync()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
 
+def region_kernel_ms(lb, steps, warmup):
+    """Average duration of the fused stream+collide kernel: HIP events on the
+    library's stream around `steps` back-to-back steps, each of which is one
+    launch of that kernel (plus a ~2.5 us iolet-series kernel per 1024 steps)."""
+    import torch
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    timed_run(lb, steps, warmup, 0, ev)
+    return ev[0].elapsed_time(ev[1]) / steps
+
+
 def kernel_avg_ms(lb, steps):
-    """Average duration of the fused stream+collide kernel from HIP events
-    recorded around each launch on the library's stream."""
+    """Average duration from HIP event pairs recorded around each launch (the
+    event records add a few microseconds per launch)."""
     lb.kernel_timing(steps)
     lb.step(steps)
     ms, k = lb.kernel_time()
@@ -239,7 +256,8 @@ def main():
     dt = timed_run(lb, args.steps, args.warmup, args.obs_every)
     glups = n * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
-    avg_ms = kernel_avg_ms(lb, args.steps)
+    avg_ms = region_kernel_ms(lb, args.steps, 10)
+    launch_ms = kernel_avg_ms(lb, args.steps)
     bpu = info["bytes_per_update"]
     achieved = bpu * n / (avg_ms * 1e-3) / 1e9
     log(f"[bench] {glups:.2f} GLUPS, {ms_step:.4f} ms/step, kernel {avg_ms:.4f} ms "
@@ -247,6 +265,7 @@ def main():
     lb.close()
 
     extra = {"bytes_per_update": bpu, "kernel_avg_ms": avg_ms,
+             "kernel_avg_ms_per_launch_events": launch_ms,
              "populations_only_GBs": (bpu - 4 * (args.lattice - 1)) * n / (avg_ms * 1e-3) / 1e9}
     # practical ceiling: plain device copy of the same byte count
     from paper_1906_11925_amd import copy_probe
@@ -271,7 +290,7 @@ def main():
                 continue
             x = make(st)
             d = timed_run(x, args.steps, args.warmup)
-            km = kernel_avg_ms(x, args.steps)
+            km = region_kernel_ms(x, args.steps, 10)
             xb = x.info()["bytes_per_update"]
             extra[st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
                          "achieved_GBs": xb * n / (km * 1e-3) / 1e9,
@@ -283,7 +302,7 @@ def main():
             for st in ("f32", "f16"):
                 x = LB.from_geometry(geom, lattice=19, storage=st)
                 d = timed_run(x, args.steps, args.warmup, args.obs_every)
-                km = kernel_avg_ms(x, args.steps)
+                km = region_kernel_ms(x, args.steps, 10)
                 xb = x.info()["bytes_per_update"]
                 extra["d3q19_" + st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
                                         "bytes_per_update": xb,
