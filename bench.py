@@ -21,13 +21,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fluid-site updates/s (GLUPS) + % HBM peak, FP32 vs FP16-store; adjoint GLUPS"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1906_11925_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11925_amd", "csrc", f)
+               for f in ("kernels.hip", "kernels.hpp", "lbdev.hpp", "lattice.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the stream-collide kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -83,14 +88,14 @@ def kernel_avg_ms(lb, steps):
     return ms / max(k, 1)
 
 
-def traffic_for(workload, storage):
+def traffic_for(workload, storage, addressing):
     """Counter-derived HBM bytes per launch, if taken on the current kernels."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    entry = rec.get(f"{workload}/{storage}")
+    entry = rec.get(f"{workload}/{storage}/{addressing}")
     if not entry or rec.get("kernel_sha") != kernel_sha():
         return None
     return entry.get("bytes_per_launch")
@@ -207,6 +212,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and adjoint runs")
     ap.add_argument("--obs-every", type=int, default=0,
                     help="also compute velocity/pressure/WSS every k steps inside the timed run")
+    ap.add_argument("--addressing", default="auto", choices=["auto", "blocks", "table16", "table32"],
+                    help="how the kernels find upstream neighbours (auto: blocks where they apply)")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed stream+collide steps (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -230,8 +237,8 @@ def main():
     n = geom.n_sites
     log(f"[bench] {n} sites ({time.perf_counter() - t0:.1f}s); creating handle")
 
-    def make(storage):
-        return LB.from_geometry(geom, lattice=args.lattice, storage=storage)
+    def make(storage, addressing=args.addressing, lattice=args.lattice):
+        return LB.from_geometry(geom, lattice=lattice, storage=storage, addressing=addressing)
 
     lb = make(args.storage)
     info = lb.info()
@@ -264,9 +271,11 @@ def main():
         f"-> {achieved:.0f} GB/s algorithmic")
     lb.close()
 
-    extra = {"bytes_per_update": bpu, "kernel_avg_ms": avg_ms,
+    pop_bytes = 2 * args.lattice * (4 if args.storage == "f32" else 2)
+    extra = {"bytes_per_update": bpu, "addressing": info["addressing_name"],
+             "kernel_avg_ms": avg_ms,
              "kernel_avg_ms_per_launch_events": launch_ms,
-             "populations_only_GBs": (bpu - 4 * (args.lattice - 1)) * n / (avg_ms * 1e-3) / 1e9}
+             "populations_only_GBs": pop_bytes * n / (avg_ms * 1e-3) / 1e9}
     # practical ceiling: plain device copy of the same byte count
     from paper_1906_11925_amd import copy_probe
     nbytes = int(bpu * n // 2 // 16) * 16
@@ -291,21 +300,37 @@ def main():
             x = make(st)
             d = timed_run(x, args.steps, args.warmup)
             km = region_kernel_ms(x, args.steps, 10)
-            xb = x.info()["bytes_per_update"]
+            xi = x.info()
+            xb = xi["bytes_per_update"]
             extra[st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
+                         "addressing": xi["addressing_name"], "bytes_per_update": xb,
                          "achieved_GBs": xb * n / (km * 1e-3) / 1e9,
                          "speedup_vs_" + args.storage: dt / d}
             log(f"[bench] {st}: {extra[st]['GLUPS']:.2f} GLUPS")
             x.close()
+        if args.addressing == "auto":
+            # the addressing form the default does not pick, for comparison
+            for st in ("f32", "f16"):
+                other = "blocks" if st == "f32" else "table16"
+                x = make(st, other)
+                d = timed_run(x, args.steps, args.warmup)
+                km = region_kernel_ms(x, args.steps, 10)
+                xb = x.info()["bytes_per_update"]
+                key = f"{other}_{st}"
+                extra[key] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
+                              "bytes_per_update": xb, "achieved_GBs": xb * n / (km * 1e-3) / 1e9}
+                log(f"[bench] {other} {st}: {extra[key]['GLUPS']:.2f} GLUPS")
+                x.close()
         if args.lattice == 15:
             # the paper's lattice on the same workload
             for st in ("f32", "f16"):
-                x = LB.from_geometry(geom, lattice=19, storage=st)
+                x = make(st, lattice=19)
                 d = timed_run(x, args.steps, args.warmup, args.obs_every)
                 km = region_kernel_ms(x, args.steps, 10)
                 xb = x.info()["bytes_per_update"]
                 extra["d3q19_" + st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
                                         "bytes_per_update": xb,
+                                        "addressing": x.info()["addressing_name"],
                                         "achieved_GBs": xb * n / (km * 1e-3) / 1e9}
                 log(f"[bench] D3Q19 {st}: {extra['d3q19_' + st]['GLUPS']:.2f} GLUPS")
                 x.close()
@@ -320,7 +345,7 @@ def main():
         log(f"[bench] cpu_baseline: oracle, {args.cpu_steps} steps")
         cpu = cpu_baseline(geom, args.lattice, args.cpu_steps)
 
-    traffic = traffic_for(args.workload, args.storage)
+    traffic = traffic_for(args.workload, args.storage, info["addressing_name"])
     line = {
         "metric": METRIC,
         "value": glups,
@@ -336,7 +361,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "sites": n, "lattice": f"D3Q{args.lattice}",
                    "storage": args.storage, "tau": geom.tau, "collision": "LBGK",
-                   "walls": "halfway bounce-back",
+                   "walls": "halfway bounce-back", "addressing": info["addressing_name"],
                    "iolets": "Ladd velocity inlet + equilibrium pressure outlets"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},

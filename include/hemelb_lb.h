@@ -65,6 +65,29 @@ typedef struct hemelb_lb* hemelb_lb_t;
 
 /* desc.flags */
 #define HEMELB_FLAG_NO_SCALE 1 /* 16-bit storage: omit the per-direction power-of-two scale */
+/* How the kernels find a site's upstream neighbours (at most one of these).  With
+ * none, 16-bit storage uses block addressing where it applies and FP32 storage the
+ * 16-bit table (the faster form of each on MI355X; the table falls back to int32
+ * where it must):
+ *   BLOCKS   two-level block addressing (the paper's decomposition of the lattice
+ *            into blocks, Section 2 and Table 2): 4x4x4 blocks, each with a fluid
+ *            bitmap, its first site index and the ids of its 26 neighbour blocks;
+ *            no per-link data.  Applies when coords are given, wall_q is NULL and
+ *            every link of nbr is the one the sites' positions imply (fluid links
+ *            join sites one lattice vector apart, iolet links of one upstream
+ *            position name the same iolet, no periodic wrap); EINVAL otherwise.
+ *   TABLE16  explicit neighbour table in 16 bits per link against per-tile lists
+ *            of source tiles (falls back to TABLE32 where a tile draws on more
+ *            than 128 source tiles)
+ *   TABLE32  explicit int32 neighbour table */
+#define HEMELB_FLAG_BLOCKS 2
+#define HEMELB_FLAG_TABLE16 4
+#define HEMELB_FLAG_TABLE32 8
+
+/* hemelb_lb_info_t.addressing */
+#define HEMELB_ADDR_TABLE32 0
+#define HEMELB_ADDR_TABLE16 1
+#define HEMELB_ADDR_BLOCKS 2
 
 /* iolet kinds */
 #define HEMELB_IOLET_PRESSURE 0
@@ -145,14 +168,18 @@ typedef struct {
 
 typedef struct {
     int64_t n_sites;     /* N */
-    int64_t n_ghosts;    /* iolet links (one ghost population each) */
-    int64_t pitch;       /* slots per direction (sites + ghost links, whole 64-site tiles) */
+    int64_t n_ghosts;    /* iolet links (one incoming population each) */
+    int64_t pitch;       /* slots per direction: sites, then ghost slots (one per iolet
+                            link, or one per upstream position with block addressing),
+                            in whole 64-site tiles */
     int64_t time;        /* completed steps (boundary time of the next step) */
     int32_t lattice;
     int32_t storage;
     double bytes_per_update;  /* algorithmic HBM bytes of one site update: populations read
-                                 and written once plus the neighbour table */
+                                 and written once plus the addressing data (neighbour
+                                 table, or block records) read once */
     int64_t device_bytes;     /* device memory held by the handle */
+    int32_t addressing;       /* HEMELB_ADDR_* in use */
 } hemelb_lb_info_t;
 
 /*
@@ -243,6 +270,16 @@ int hemelb_lb_set_deviations(hemelb_lb_t h, const float* src, int64_t t);
 
 /* Sizes, time and byte counts of a handle (host `info`). */
 int hemelb_lb_info(hemelb_lb_t h, hemelb_lb_info_t* info);
+
+/*
+ * Plan without a device: validate `d` exactly as hemelb_lb_create does and report
+ * the layout it would build (host `info`: n_sites, n_ghosts, pitch, addressing,
+ * bytes_per_update, and device_bytes = the device memory create would allocate;
+ * time is 0).  Runs on the host only, so it also serves to size a run before a
+ * GPU is at hand.  Errors: those of hemelb_lb_create's validation (EINVAL, with
+ * the same messages), ENOMEM.
+ */
+int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info);
 
 /*
  * Kernel timing with HIP events recorded on the handle's stream around every

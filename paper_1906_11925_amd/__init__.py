@@ -5,5 +5,5 @@ ABI of ``include/hemelb_lb.h``); this package holds its ctypes binding and
 build script.  Importing it does not touch the GPU.
 """
 
-from .lb import LB, links, copy_probe, relaxation_time  # noqa: F401
+from .lb import LB, links, plan, plan_geometry, copy_probe, relaxation_time  # noqa: F401
 from .lib import HemelbError, load  # noqa: F401

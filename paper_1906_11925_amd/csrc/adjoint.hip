@@ -114,14 +114,14 @@ __global__ __launch_bounds__(kObjBlock) void k_objective(
         const int32_t s = G.site[l];
         const int i = G.dir[l];
         const int o = opp(i);
-        q += (double)C::dec(o, A[tix<Q>(o, s)]) - (double)C::dec(i, A[tix<Q>(i, n + l)]);
+        q += (double)C::dec(o, A[tix<Q>(o, s)]) -
+             (double)C::dec(i, A[tix<Q>(i, ghost_slot(G, n, l))]);
     }
     for (int32_t k = threadIdx.x; k < n_dome; k += kObjBlock) {
         const int32_t s = dome[k];
         float d[Q];
         int32_t j[Q];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) j[i] = link_one<Q>(tb, s, i);
+        links_site<Q>(tb, s, j);
         gather_pre<Q, ST, SC>(A, s, n, d, j);
         float drho, mx, my, mz;
         moments<Q>(d, drho, mx, my, mz);
@@ -149,12 +149,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal) {
     using Lt = Lat<Q>;
-    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-    if ((s & ~(kTile - 1)) >= n) return;
+    static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
+    __shared__ StageLds lds;
+    const int32_t grp = blockIdx.x;
+    const int32_t s = grp * kBlock + threadIdx.x;
+    const bool live = (s & ~(kTile - 1)) < n;
     float d[Q];
     int32_t j[Q];
-    links_wave<Q, false>(tb, s, j);
-    if (s >= n) return;
+    links_group<Q, false>(tb, grp, s, live, lds, j);
+    if (!live || s >= n) return;
     gather_pre<Q, ST, SC>(A, s, n, d, j);
     float g[Q];
 #pragma unroll
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_iolet(
         const int o = opp(i);
         const int kio = G.iolet[l];
         const DevIolet io = G.iolets[kio];
-        float gh = gout[tix<Q>(i, n + l)];
+        float gh = gout[tix<Q>(i, ghost_slot(G, n, l))];
         if (kio == outlet && q_index >= 0) {
             gh -= (float)qbar;
             acc[o] += (float)qbar;

@@ -12,6 +12,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hemelb_lb.h"
@@ -139,6 +140,16 @@ struct hemelb_lb {
     int32_t* toff = nullptr;
     int32_t* tlist = nullptr;
     int64_t tlist_len = 0;
+    hlb::BlockRec* brec = nullptr;  // block addressing
+    uint64_t* gmask = nullptr;
+    int32_t* bnbr = nullptr;
+    int32_t* tblock = nullptr;
+    int32_t nfluid = 0, nblocks = 0;
+    int addressing = HEMELB_ADDR_TABLE32;
+    int32_t* g_slot = nullptr;  // ghost slot of each iolet link (block addressing)
+    uint32_t* gblob = nullptr;  // staged block records per 4-tile group
+    int32_t* grp = nullptr;
+    int64_t blob_words = 0;
     int32_t* g_site = nullptr;
     uint8_t* g_dir = nullptr;
     uint8_t* g_iolet = nullptr;
@@ -207,22 +218,24 @@ struct hemelb_lb {
     int64_t adj_t = -1;
 
     hlb::Layout layout() const {
-        return hlb::Layout{q, storage, scaled, n, slots, hlb::Table{tbl, t16, toff, tlist}};
+        return hlb::Layout{q, storage, scaled, n, slots,
+                           hlb::Table{tbl, t16, toff, tlist, brec, gmask, bnbr, tblock,
+                                      reinterpret_cast<const uint4*>(gblob), grp, nfluid, nblocks,
+                                      (int32_t)n},
+                           bfl};
     }
     hlb::Ghosts ghosts() const {
-        return hlb::Ghosts{nghost,  g_site, g_dir,   g_iolet,  g_coef,
+        return hlb::Ghosts{nghost,   g_slot, g_site, g_dir,   g_iolet,  g_coef,
                            d_iolets, d_harm, d_vals, vals_t0, n_iolets};
     }
     size_t elem() const { return storage == HEMELB_STORE_F32 ? 4 : 2; }
     // algorithmic HBM bytes of one site update: populations read and written once,
-    // plus the neighbour table (and the compact table's per-tile lists)
+    // plus the addressing data read once (the neighbour table and the compact
+    // table's per-tile lists, or the block records, neighbour-block ids and per-tile
+    // first blocks)
+    double addr_bytes = 0;  // addressing data one step reads (see HostPlan)
     double bytes_per_update() const {
-        double b = 2.0 * q * (double)elem();
-        if (t16)
-            b += 2.0 * (q - 1) + (n > 0 ? 4.0 * (double)(tlist_len + ttiles + 1) / (double)n : 0.0);
-        else
-            b += 4.0 * (q - 1);
-        return b;
+        return 2.0 * q * (double)elem() + (n > 0 ? addr_bytes / (double)n : 0.0);
     }
 };
 
@@ -252,7 +265,8 @@ void release(hemelb_lb* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
-                    h->t16,       h->toff,      h->tlist,
+                    h->t16,       h->toff,      h->tlist,      h->brec,      h->gmask,
+                    h->bnbr,      h->tblock,    h->g_slot,     h->gblob,     h->grp,
                     h->g_iolet,   h->g_coef,    h->d_iolets,   h->d_harm,    h->perm,
                     h->normal,    h->alpha,     h->partial,    h->tot,       h->flag,
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
@@ -272,7 +286,12 @@ int validate(const hemelb_lb_desc_t* d) {
         return fail(HEMELB_EINVAL, "lattice must be 15 or 19 (got %d)", d->lattice);
     if (d->storage < HEMELB_STORE_F32 || d->storage > HEMELB_STORE_BF16)
         return fail(HEMELB_EINVAL, "unknown storage %d", d->storage);
-    if (d->flags & ~HEMELB_FLAG_NO_SCALE) return fail(HEMELB_EINVAL, "unknown flags 0x%x", d->flags);
+    const int32_t known = HEMELB_FLAG_NO_SCALE | HEMELB_FLAG_BLOCKS | HEMELB_FLAG_TABLE16 |
+                          HEMELB_FLAG_TABLE32;
+    if (d->flags & ~known) return fail(HEMELB_EINVAL, "unknown flags 0x%x", d->flags);
+    const int32_t addr = d->flags & (HEMELB_FLAG_BLOCKS | HEMELB_FLAG_TABLE16 | HEMELB_FLAG_TABLE32);
+    if (addr & (addr - 1))
+        return fail(HEMELB_EINVAL, "at most one of the BLOCKS, TABLE16 and TABLE32 flags");
     if (d->n_sites < 0) return fail(HEMELB_EINVAL, "n_sites < 0");
     if (d->n_sites >= (int64_t)1 << 30) return fail(HEMELB_EINVAL, "n_sites must be below 2^30");
     if (!(d->tau > 0.5)) return fail(HEMELB_EINVAL, "tau must exceed 1/2 (got %g)", d->tau);
@@ -345,6 +364,288 @@ int validate(const hemelb_lb_desc_t* d) {
     return HEMELB_OK;
 }
 
+// Two-level block addressing (the lattice cut into 4x4x4 blocks).  Built from the
+// Morton-ordered sites; applies only when every link of the caller's table is the
+// one the sites' positions imply, which is checked link by link.
+struct BlockPlan {
+    std::vector<hlb::BlockRec> rec;  // fluid blocks in site order, then ghost-only blocks
+    std::vector<uint64_t> gmask;
+    std::vector<int32_t> nbr;        // [nfluid][27]
+    std::vector<int32_t> tblock;     // block of the first site of each tile
+    std::vector<int32_t> gslot;      // ghost slot of each iolet link
+    std::vector<uint32_t> blob;      // staged records of every 4-tile group (16-byte units)
+    std::vector<int32_t> grp;        // per group: blob offset, nown | nrec << 16
+    double fallback_bytes = 0;       // global records read by groups whose blob would not fit
+    int32_t nfluid = 0;
+    int64_t ncells = 0;
+    std::string why;                 // reason it does not apply
+};
+
+inline int block_pos(int x, int y, int z) {
+    return (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((x & 2) << 2) | ((y & 2) << 3) |
+           ((z & 2) << 4);
+}
+
+inline uint64_t block_key(int64_t bx, int64_t by, int64_t bz) {  // each in [-1, 2^21)
+    return ((uint64_t)(bx + 1) << 42) | ((uint64_t)(by + 1) << 21) | (uint64_t)(bz + 1);
+}
+
+inline uint64_t rec_mask(const hlb::BlockRec& r) {
+    return ((uint64_t)r.mask_hi << 32) | (uint64_t)r.mask_lo;
+}
+
+// order: Morton index -> caller index; inv: its inverse; gbase[m]: first iolet link
+// of Morton site m; gsite/gdir/giol: the iolet links (site, direction, iolet)
+bool build_blocks(const hemelb_lb_desc_t* d, const HostLat& lat, const std::vector<int32_t>& order,
+                  const std::vector<int32_t>& inv, const std::vector<int64_t>& gbase,
+                  const std::vector<int32_t>& gsite, const std::vector<uint8_t>& gdir,
+                  const std::vector<uint8_t>& giol, int64_t ttiles, BlockPlan& P) {
+    const int q = d->lattice;
+    const int64_t n = d->n_sites;
+    const int64_t ng = (int64_t)gsite.size();
+    auto X = [&](int64_t m, int a) -> int64_t { return d->coords[3 * (int64_t)order[m] + a]; };
+    std::unordered_map<uint64_t, int32_t> id;
+    id.reserve((size_t)(n / 16 + ng + 16));
+    std::vector<int64_t> bc;  // block coordinates, 3 per block
+    std::vector<int32_t> site_block(n);
+    uint64_t last = ~0ull;
+    for (int64_t m = 0; m < n; ++m) {
+        const int64_t x = X(m, 0), y = X(m, 1), z = X(m, 2);
+        const uint64_t k = block_key(x >> 2, y >> 2, z >> 2);
+        if (k != last) {
+            // Morton order keeps each block's sites together
+            if (!id.emplace(k, (int32_t)P.rec.size()).second) {
+                P.why = "internal: sites of a block are not contiguous";
+                return false;
+            }
+            P.rec.push_back(hlb::BlockRec{0u, 0u, (int32_t)m, -1});
+            bc.insert(bc.end(), {x >> 2, y >> 2, z >> 2});
+            last = k;
+        }
+        const int p = block_pos((int)(x & 3), (int)(y & 3), (int)(z & 3));
+        if (p < 32)
+            P.rec.back().mask_lo |= 1u << p;
+        else
+            P.rec.back().mask_hi |= 1u << (p - 32);
+        site_block[m] = (int32_t)P.rec.size() - 1;
+    }
+    P.nfluid = (int32_t)P.rec.size();
+
+    // ghost cells: the positions past iolet planes that iolet links pull from
+    struct Cell {
+        int32_t block, pos, iolet;
+        int64_t link;
+    };
+    std::vector<Cell> cells((size_t)ng);
+    for (int64_t l = 0; l < ng; ++l) {
+        const int i = gdir[l];
+        const int64_t m = gsite[l];
+        const int64_t x = X(m, 0) - lat.c[i][0], y = X(m, 1) - lat.c[i][1], z = X(m, 2) - lat.c[i][2];
+        const uint64_t k = block_key(x >> 2, y >> 2, z >> 2);
+        auto it = id.find(k);
+        int32_t b;
+        if (it == id.end()) {
+            b = (int32_t)P.rec.size();
+            id.emplace(k, b);
+            P.rec.push_back(hlb::BlockRec{0u, 0u, (int32_t)n, -1});
+            bc.insert(bc.end(), {x >> 2, y >> 2, z >> 2});
+        } else {
+            b = it->second;
+        }
+        const int p = block_pos((int)(x & 3), (int)(y & 3), (int)(z & 3));
+        if ((rec_mask(P.rec[b]) >> p) & 1ull) {
+            P.why = "an iolet link pulls from the position of a fluid site";
+            return false;
+        }
+        cells[l] = Cell{b, p, giol[l], l};
+    }
+    std::sort(cells.begin(), cells.end(), [](const Cell& a, const Cell& b) {
+        return a.block < b.block || (a.block == b.block && a.pos < b.pos);
+    });
+    P.gmask.assign(P.rec.size(), 0ull);
+    P.gslot.assign((size_t)ng, 0);
+    int64_t g = -1;
+    for (size_t e = 0; e < cells.size(); ++e) {
+        const Cell& c = cells[e];
+        if (e == 0 || c.block != cells[e - 1].block || c.pos != cells[e - 1].pos) {
+            ++g;
+            if (P.rec[c.block].goff < 0) P.rec[c.block].goff = (int32_t)g;
+            P.gmask[c.block] |= 1ull << c.pos;
+        } else if (c.iolet != cells[e - 1].iolet) {
+            P.why = "one position past an iolet plane is named with two iolet ids";
+            return false;
+        }
+        P.gslot[c.link] = (int32_t)(n + g);
+    }
+    P.ncells = g + 1;
+
+    // the 27 blocks around every fluid block
+    P.nbr.assign((size_t)P.nfluid * 27, -1);
+    parallel_for(P.nfluid, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k)
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        auto it = id.find(block_key(bc[3 * k] + dx, bc[3 * k + 1] + dy,
+                                                    bc[3 * k + 2] + dz));
+                        if (it != id.end())
+                            P.nbr[(size_t)k * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] = it->second;
+                    }
+    });
+
+    // every link must decode to what the caller's table says
+    std::atomic<int64_t> bad{-1};
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b && bad.load(std::memory_order_relaxed) < 0; ++m) {
+            const int64_t s = order[m];
+            const int32_t bl = site_block[m];
+            const int bx = (int)(X(m, 0) & 3), by = (int)(X(m, 1) & 3), bz = (int)(X(m, 2) & 3);
+            int64_t gl = gbase[m];
+            for (int i = 1; i < q; ++i) {
+                const int32_t v = d->nbr[s * q + i];
+                int32_t want;
+                if (v >= 0)
+                    want = inv[v];
+                else if (v == HEMELB_LINK_WALL)
+                    want = (int32_t)0x80000000u;
+                else
+                    want = P.gslot[gl++];
+                const int ux = bx - lat.c[i][0], uy = by - lat.c[i][1], uz = bz - lat.c[i][2];
+                const int dd = ((ux >> 2) + 1) + 3 * ((uy >> 2) + 1) + 9 * ((uz >> 2) + 1);
+                const int32_t b2 = P.nbr[(size_t)bl * 27 + dd];
+                int32_t got = (int32_t)0x80000000u;
+                if (b2 >= 0) {
+                    const uint64_t mk = rec_mask(P.rec[b2]);
+                    const int p = block_pos(ux & 3, uy & 3, uz & 3);
+                    const uint64_t below = (1ull << p) - 1ull;
+                    if ((mk >> p) & 1ull)
+                        got = P.rec[b2].off + __builtin_popcountll(mk & below);
+                    else if ((P.gmask[b2] >> p) & 1ull)
+                        got = (int32_t)n + P.rec[b2].goff + __builtin_popcountll(P.gmask[b2] & below);
+                }
+                if (got != want) {
+                    int64_t none = -1;
+                    bad.compare_exchange_strong(none, s * q + i);
+                    break;
+                }
+            }
+        }
+    });
+    if (bad.load() >= 0) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "link (site %lld, direction %d) is not the one the site positions imply",
+                 (long long)(bad.load() / q), (int)(bad.load() % q));
+        P.why = buf;
+        return false;
+    }
+    P.tblock.assign((size_t)ttiles, 0);
+    for (int64_t T = 0; T < ttiles; ++T) P.tblock[T] = site_block[std::min(T * hlb::kTile, n - 1)];
+
+    // staged records of each group of four tiles (one 256-thread workgroup)
+    const int64_t groups = (ttiles + 3) / 4;
+    P.grp.assign((size_t)groups * 2, 0);
+    std::vector<int32_t> recs;
+    std::vector<uint8_t> rows;
+    for (int64_t g = 0; g < groups; ++g) {
+        const int64_t s0 = g * 4 * hlb::kTile, s1 = std::min(s0 + 4 * hlb::kTile, n) - 1;
+        const int32_t b_lo = site_block[s0], b_hi = site_block[s1];
+        const int nown = b_hi - b_lo + 1;
+        P.grp[2 * g] = (int32_t)(P.blob.size() / 4);
+        // a group left at nown = 0 reads, per own block, its record, neighbour ids and the
+        // neighbours' records
+        const double global_bytes = (double)nown * (sizeof(hlb::BlockRec) + 27 * 4 + 8);
+        if (nown > hlb::kStageRows) {
+            P.fallback_bytes += global_bytes;
+            continue;
+        }
+        recs.clear();
+        for (int32_t b = b_lo; b <= b_hi; ++b) recs.push_back(b);
+        rows.assign((size_t)nown * hlb::kRowBytes, 0xff);
+        bool fits = true;
+        for (int k = 0; k < nown && fits; ++k)
+            for (int dd = 0; dd < 27; ++dd) {
+                const int32_t nb = P.nbr[(size_t)(b_lo + k) * 27 + dd];  // -1: the empty record
+                int idx = (int)(std::find(recs.begin(), recs.end(), nb) - recs.begin());
+                if (idx == (int)recs.size()) {
+                    if ((int)recs.size() == hlb::kStageRecs) {
+                        fits = false;
+                        break;
+                    }
+                    recs.push_back(nb);
+                }
+                rows[(size_t)k * hlb::kRowBytes + dd] = (uint8_t)idx;
+            }
+        if (!fits) {
+            P.fallback_bytes += global_bytes;
+            continue;
+        }
+        const size_t row_words = (size_t)((nown * hlb::kRowBytes + 15) / 16) * 4;
+        const size_t at = P.blob.size();
+        P.blob.resize(at + row_words + recs.size() * 4, 0);
+        std::memcpy(&P.blob[at], rows.data(), rows.size());
+        for (size_t r = 0; r < recs.size(); ++r) {
+            hlb::BlockRec c{0u, 0u, 0, -1};  // no block there: no fluid, no ghost cells
+            if (recs[r] >= 0) {
+                c = P.rec[recs[r]];
+                c.goff = c.goff >= 0 ? recs[r] : -1;  // staged copies name ghost blocks by id
+            }
+            std::memcpy(&P.blob[at + row_words + 4 * r], &c, sizeof c);
+        }
+        P.grp[2 * g + 1] = nown | (int32_t)(recs.size() << 16);
+    }
+    if (P.blob.empty()) P.blob.assign(4, 0);
+
+    // the staged copies must decode every link as the caller's table says (the
+    // same steps the kernels take, on the host)
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b && bad.load(std::memory_order_relaxed) < 0; ++m) {
+            const int64_t g = m / (4 * hlb::kTile);
+            const int nown = P.grp[2 * g + 1] & 0xffff;
+            if (nown == 0) continue;
+            const uint8_t* bytes = reinterpret_cast<const uint8_t*>(&P.blob[4 * (size_t)P.grp[2 * g]]);
+            const hlb::BlockRec* recs =
+                reinterpret_cast<const hlb::BlockRec*>(bytes + 16 * ((nown * hlb::kRowBytes + 15) / 16));
+            int k = 0;
+            for (int qq = 1; qq < nown; ++qq)
+                if (m >= recs[qq].off) k = qq;
+            const uint64_t om = rec_mask(recs[k]);
+            int rank = (int)(m - recs[k].off), p = 0;
+            for (; p < 64; ++p)
+                if (((om >> p) & 1ull) && rank-- == 0) break;
+            const int bx = (p & 1) | ((p >> 2) & 2), by = ((p >> 1) & 1) | ((p >> 3) & 2),
+                      bz = ((p >> 2) & 1) | ((p >> 4) & 2);
+            const int64_t s = order[m];
+            int64_t gl = gbase[m];
+            for (int i = 1; i < q; ++i) {
+                const int32_t v = d->nbr[s * q + i];
+                const int32_t want = v >= 0 ? inv[v]
+                                   : v == HEMELB_LINK_WALL ? (int32_t)0x80000000u : P.gslot[gl++];
+                const int ux = bx - lat.c[i][0], uy = by - lat.c[i][1], uz = bz - lat.c[i][2];
+                const int dd = ((ux >> 2) + 1) + 3 * ((uy >> 2) + 1) + 9 * ((uz >> 2) + 1);
+                const hlb::BlockRec& r = recs[bytes[k * hlb::kRowBytes + dd]];
+                const int pp = block_pos(ux & 3, uy & 3, uz & 3);
+                const uint64_t mk = rec_mask(r), below = (1ull << pp) - 1ull;
+                int32_t got = (int32_t)0x80000000u;
+                if ((mk >> pp) & 1ull)
+                    got = r.off + __builtin_popcountll(mk & below);
+                else if (r.goff >= 0 && ((P.gmask[r.goff] >> pp) & 1ull))
+                    got = (int32_t)n + P.rec[r.goff].goff + __builtin_popcountll(P.gmask[r.goff] & below);
+                if (got != want) {
+                    int64_t none = -1;
+                    bad.compare_exchange_strong(none, s * q + i);
+                    break;
+                }
+            }
+        }
+    });
+    if (bad.load() >= 0) {
+        P.why = "internal: a staged block record decodes a link wrongly";
+        return false;
+    }
+    return true;
+}
+
 // iolet values for times t0 .. t0 + count - 1 into the handle's table
 int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
     if (h->n_iolets == 0) return HEMELB_OK;
@@ -405,6 +706,245 @@ int check_flag(hemelb_lb* h) {
     HIP_TRY(hipMemcpy(&f, h->flag, sizeof f, hipMemcpyDeviceToHost), "flag readback");
     if (f) return fail(HEMELB_EDIVERGED, "non-finite density or momentum detected");
     return HEMELB_OK;
+}
+
+// Everything create builds on the host before any device work.
+struct HostPlan {
+    int64_t n = 0, nghost = 0, slots = 0, ttiles = 0;
+    std::vector<int32_t> order, inv;  // Morton index -> caller index, and back
+    std::vector<int32_t> gsite;       // iolet links in Morton site order, direction ascending
+    std::vector<uint8_t> gdir, giol;
+    std::vector<float> gcoef;
+    int addressing = HEMELB_ADDR_TABLE32;
+    BlockPlan bp;                     // block addressing
+    std::vector<int32_t> tbl;         // int32 table
+    std::vector<uint16_t> t16;        // compact table
+    std::vector<int32_t> toff, tlist;
+    std::vector<float> nrm;           // wall normals [3][n], Morton order
+    std::vector<hlb::DevIolet> dio;
+    std::vector<double> harm;
+    std::vector<float> alpha;
+    std::vector<int32_t> perm;
+    double addr_bytes = 0;  // addressing data one step reads: the table, or the staged
+                            // block records and group entries (plus global records of
+                            // groups whose staged copy would not fit) and tile blocks
+};
+
+// Validate d and build the host side of its layout (no device work).
+int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
+    int rc = validate(d);
+    if (rc) return rc;
+    const int q = d->lattice;
+    const int64_t n = d->n_sites;
+    P.n = n;
+    const HostLat lat = host_lattice(q);
+
+    // Morton order: order[m] = caller index of the m-th site
+    P.order.resize(n);
+    P.inv.resize(n);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    if (d->coords && n > 0) {
+        struct KI {
+            uint64_t key;
+            int32_t idx;
+        };
+        std::vector<KI> ki(n);
+        parallel_for(n, [&](int64_t a, int64_t b) {
+            for (int64_t s = a; s < b; ++s) {
+                const int32_t* c = d->coords + 3 * s;
+                ki[s] = KI{morton(c[0], c[1], c[2]), (int32_t)s};
+            }
+        });
+        std::sort(ki.begin(), ki.end(), [](const KI& a, const KI& b) {
+            return a.key < b.key || (a.key == b.key && a.idx < b.idx);
+        });
+        for (int64_t m = 0; m < n; ++m) P.order[m] = ki[m].idx;
+        for (int64_t m = 1; m < n; ++m)
+            if (ki[m].key == ki[m - 1].key)
+                return fail(HEMELB_EINVAL, "duplicate coordinates at sites %d and %d",
+                            ki[m - 1].idx, ki[m].idx);
+    }
+    for (int64_t m = 0; m < n; ++m) P.inv[P.order[m]] = (int32_t)m;
+
+    // iolet links in Morton site order, direction ascending
+    for (int64_t m = 0; m < n; ++m) {
+        const int64_t s = P.order[m];
+        for (int i = 1; i < q; ++i) {
+            const int32_t v = d->nbr[s * q + i];
+            if (v <= -2) {
+                const int k = -2 - v;
+                P.gsite.push_back((int32_t)m);
+                P.gdir.push_back((uint8_t)i);
+                P.giol.push_back((uint8_t)k);
+                double coef = 0.0;
+                const hemelb_iolet_t& io = d->iolets[k];
+                if (io.kind == HEMELB_IOLET_VELOCITY) {
+                    const double W = d->site_weight ? d->site_weight[s] : 1.0;
+                    const double ce = lat.c[i][0] * io.direction[0] + lat.c[i][1] * io.direction[1] +
+                                      lat.c[i][2] * io.direction[2];
+                    coef = 6.0 * lat.w[i] * ce * W;
+                }
+                P.gcoef.push_back((float)coef);
+            }
+        }
+    }
+    P.nghost = (int64_t)P.gsite.size();
+    if (n + P.nghost >= ((int64_t)1 << 30))
+        return fail(HEMELB_EINVAL, "sites + iolet links must stay below 2^30");
+    P.ttiles = std::max<int64_t>(1, (n + hlb::kTile - 1) / hlb::kTile);
+    std::vector<int64_t> gbase(n + 1, 0);  // first iolet link of each Morton site
+    for (int64_t l = 0; l < P.nghost; ++l) gbase[P.gsite[l] + 1]++;
+    for (int64_t m = 0; m < n; ++m) gbase[m + 1] += gbase[m];
+
+    // addressing: asked for, or by default block addressing for 16-bit storage (where
+    // it applies) and the explicit table otherwise -- the faster form of each on
+    // MI355X (with FP32 storage the table's extra bytes cost less than the block
+    // decode's longer chain of dependent loads)
+    bool blocks = false;
+    const bool try_blocks = (d->flags & HEMELB_FLAG_BLOCKS) ||
+                            (!(d->flags & (HEMELB_FLAG_TABLE16 | HEMELB_FLAG_TABLE32)) &&
+                             d->storage != HEMELB_STORE_F32);
+    if (try_blocks && n > 0) {
+        if (!d->coords)
+            P.bp.why = "it needs site coordinates";
+        else if (d->wall_q)
+            P.bp.why = "interpolated walls need the neighbour table";
+        else
+            blocks = build_blocks(d, lat, P.order, P.inv, gbase, P.gsite, P.gdir, P.giol, P.ttiles,
+                                  P.bp);
+    }
+    if ((d->flags & HEMELB_FLAG_BLOCKS) && n > 0 && !blocks)
+        return fail(HEMELB_EINVAL, "block addressing does not apply: %s", P.bp.why.c_str());
+    const int64_t ghost_slots = blocks ? P.bp.ncells : P.nghost;
+    P.slots = std::max<int64_t>(hlb::kTile, ((n + ghost_slots + hlb::kTile - 1) / hlb::kTile) * hlb::kTile);
+
+    if (blocks) {
+        P.addressing = HEMELB_ADDR_BLOCKS;
+        P.addr_bytes = 4.0 * (double)(P.bp.blob.size() + P.bp.grp.size()) + P.bp.fallback_bytes;
+    } else {
+        // pull table [tile][q-1][64]: fluid -> Morton index of the upstream site;
+        // wall -> bit 31 set (read the opposite direction of the same site) with the
+        // interpolated-wall fraction in units of 2^-15 in the low bits (0: halfway);
+        // iolet -> ghost slot n + l
+        std::vector<int32_t> tbl((size_t)P.ttiles * (q - 1) * hlb::kTile, 0);
+        for (int64_t m = 0; m < n; ++m) {
+            const int64_t s = P.order[m];
+            int64_t g = gbase[m];
+            for (int i = 1; i < q; ++i) {
+                const int32_t v = d->nbr[s * q + i];
+                uint32_t e;
+                if (v >= 0)
+                    e = (uint32_t)P.inv[v];
+                else if (v == HEMELB_LINK_WALL)
+                    e = 0x80000000u | (d->wall_q ? wall_code(d->wall_q[s * q + i]) : 0u);
+                else
+                    e = (uint32_t)(n + (g++));
+                const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
+                                  (size_t)(m % hlb::kTile);
+                tbl[at] = (int32_t)e;
+            }
+        }
+        // compact form: 16-bit codes against a per-tile list of source tiles
+        bool compact = !(d->flags & HEMELB_FLAG_TABLE32);
+        if (compact) {
+            P.t16.assign(tbl.size(), 0);
+            P.toff.assign((size_t)P.ttiles + 1, 0);
+            std::vector<int32_t> tiles;
+            for (int64_t T = 0; T < P.ttiles && compact; ++T) {
+                tiles.clear();
+                const size_t base = (size_t)T * (q - 1) * hlb::kTile;
+                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
+                    const int32_t v = tbl[base + e];
+                    if (v >= 0) tiles.push_back(v >> hlb::kTileShift);
+                }
+                std::sort(tiles.begin(), tiles.end());
+                tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+                if (tiles.size() > 2 * (size_t)hlb::kTile) {
+                    compact = false;
+                    break;
+                }
+                P.toff[T] = (int32_t)P.tlist.size();
+                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
+                    const int32_t v = tbl[base + e];
+                    uint16_t c;
+                    if (v < 0) {
+                        c = (uint16_t)(0x8000u | ((uint32_t)v & 0x7fffu));
+                    } else {
+                        const int32_t slot = (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
+                                                                        v >> hlb::kTileShift) -
+                                                       tiles.begin());
+                        c = (uint16_t)((slot << hlb::kTileShift) | (v & (hlb::kTile - 1)));
+                    }
+                    P.t16[base + e] = c;
+                }
+                P.tlist.insert(P.tlist.end(), tiles.begin(), tiles.end());
+            }
+            P.toff[P.ttiles] = (int32_t)P.tlist.size();
+        }
+        if (compact) {
+            if (P.tlist.empty()) P.tlist.push_back(0);
+            P.addressing = HEMELB_ADDR_TABLE16;
+            P.addr_bytes = 2.0 * (q - 1) * (double)n + 4.0 * (double)(P.toff.size() + P.tlist.size());
+        } else {
+            P.t16.clear();
+            P.toff.clear();
+            P.tlist.clear();
+            P.tbl = std::move(tbl);
+            P.addr_bytes = 4.0 * (q - 1) * (double)n;
+        }
+    }
+
+    // wall normals [3][n] in Morton order
+    P.nrm.assign((size_t)3 * n, 0.f);
+    for (int64_t m = 0; m < n; ++m) {
+        const int64_t s = P.order[m];
+        double v[3] = {0, 0, 0};
+        if (d->wall_normal) {
+            for (int a = 0; a < 3; ++a) v[a] = d->wall_normal[3 * s + a];
+        } else {
+            for (int i = 1; i < q; ++i)
+                if (d->nbr[s * q + i] == HEMELB_LINK_WALL)
+                    for (int a = 0; a < 3; ++a) v[a] += lat.c[i][a];
+        }
+        const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (nn > 0)
+            for (int a = 0; a < 3; ++a) P.nrm[(size_t)a * n + m] = (float)(v[a] / nn);
+    }
+
+    // iolet descriptors and harmonics
+    P.dio.resize(d->n_iolets);
+    for (int k = 0; k < d->n_iolets; ++k) {
+        const hemelb_iolet_t& io = d->iolets[k];
+        P.dio[k].kind = io.kind == HEMELB_IOLET_PRESSURE ? 0 : 1;
+        P.dio[k].n_harm = io.n_harm;
+        P.dio[k].harm_off = (int32_t)P.harm.size();
+        P.dio[k].pad = 0;
+        P.dio[k].mean = io.mean;
+        P.dio[k].period = io.n_harm > 0 ? io.period : 1.0;
+        for (int hh = 0; hh < io.n_harm; ++hh) P.harm.push_back(io.cos_k[hh]);
+        for (int hh = 0; hh < io.n_harm; ++hh) P.harm.push_back(io.sin_k[hh]);
+    }
+    if (d->coords) P.perm = P.order;
+    if (d->alpha) {
+        P.alpha.resize(n);
+        for (int64_t m = 0; m < n; ++m) P.alpha[m] = d->alpha[P.order[m]];
+    }
+    return HEMELB_OK;
+}
+
+// Device bytes of the arrays create allocates for plan P (population buffers,
+// addressing data, ghost lists, normals, alpha, permutation, reductions).
+int64_t planned_device_bytes(const HostPlan& P, int q, size_t elem) {
+    int64_t b = 2 * (int64_t)q * P.slots * (int64_t)elem;
+    b += (int64_t)(P.bp.rec.size() * sizeof(hlb::BlockRec) + P.bp.gmask.size() * 8 +
+                   P.bp.nbr.size() * 4 + P.bp.tblock.size() * 4 + P.bp.gslot.size() * 4 +
+                   P.bp.blob.size() * 4 + P.bp.grp.size() * 4);
+    b += (int64_t)(P.tbl.size() * 4 + P.t16.size() * 2 + P.toff.size() * 4 + P.tlist.size() * 4);
+    b += (int64_t)(P.gsite.size() * 4 + P.gdir.size() + P.giol.size() + P.gcoef.size() * 4);
+    b += (int64_t)(P.dio.size() * sizeof(hlb::DevIolet) + P.harm.size() * 8);
+    b += (int64_t)(P.perm.size() * 4 + P.nrm.size() * 4 + P.alpha.size() * 4);
+    b += hlb::totals_parts(P.n) * 4 * 8 + 4 * 8 + 4;
+    return b;
 }
 
 }  // namespace
@@ -522,10 +1062,30 @@ int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t
     return HEMELB_OK;
 }
 
+int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
+    if (!info) return fail(HEMELB_EINVAL, "info is NULL");
+    HostPlan P;
+    int rc = make_plan(d, P);
+    if (rc) return rc;
+    const size_t elem = d->storage == HEMELB_STORE_F32 ? 4 : 2;
+    info->n_sites = P.n;
+    info->n_ghosts = P.nghost;
+    info->pitch = P.slots;
+    info->time = 0;
+    info->lattice = d->lattice;
+    info->storage = d->storage;
+    info->bytes_per_update =
+        2.0 * d->lattice * (double)elem + (P.n > 0 ? P.addr_bytes / (double)P.n : 0.0);
+    info->device_bytes = planned_device_bytes(P, d->lattice, elem);
+    info->addressing = P.addressing;
+    return HEMELB_OK;
+}
+
 int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     if (!out) return fail(HEMELB_EINVAL, "out is NULL");
     *out = nullptr;
-    int rc = validate(d);
+    HostPlan P;
+    int rc = make_plan(d, P);
     if (rc) return rc;
     hemelb_lb* h = new (std::nothrow) hemelb_lb();
     if (!h) return fail(HEMELB_ENOMEM, "handle allocation failed");
@@ -542,148 +1102,23 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     (void)hipGetDevice(&h->device);
     const int q = h->q;
     const int64_t n = h->n;
-    const HostLat lat = host_lattice(q);
-
-    // Morton order: order[m] = caller index of the m-th site
-    std::vector<int32_t> order(n), inv(n);
-    std::iota(order.begin(), order.end(), 0);
-    if (d->coords && n > 0) {
-        struct KI {
-            uint64_t key;
-            int32_t idx;
-        };
-        std::vector<KI> ki(n);
-        parallel_for(n, [&](int64_t a, int64_t b) {
-            for (int64_t s = a; s < b; ++s)
-                ki[s] = KI{morton(d->coords[3 * s], d->coords[3 * s + 1], d->coords[3 * s + 2]),
-                           (int32_t)s};
-        });
-        std::sort(ki.begin(), ki.end(), [](const KI& a, const KI& b) {
-            return a.key < b.key || (a.key == b.key && a.idx < b.idx);
-        });
-        for (int64_t m = 0; m < n; ++m) order[m] = ki[m].idx;
-        for (int64_t m = 1; m < n; ++m)
-            if (ki[m].key == ki[m - 1].key) {
-                delete h;
-                return fail(HEMELB_EINVAL, "duplicate coordinates at sites %d and %d",
-                            ki[m - 1].idx, ki[m].idx);
-            }
-    }
-    for (int64_t m = 0; m < n; ++m) inv[order[m]] = (int32_t)m;
-
-    // ghost links in Morton site order, direction ascending
-    std::vector<int32_t> gsite;
-    std::vector<uint8_t> gdir, giol;
-    std::vector<float> gcoef;
-    for (int64_t m = 0; m < n; ++m) {
-        const int64_t s = order[m];
-        for (int i = 1; i < q; ++i) {
-            const int32_t v = d->nbr[s * q + i];
-            if (v <= -2) {
-                const int k = -2 - v;
-                gsite.push_back((int32_t)m);
-                gdir.push_back((uint8_t)i);
-                giol.push_back((uint8_t)k);
-                double coef = 0.0;
-                const hemelb_iolet_t& io = d->iolets[k];
-                if (io.kind == HEMELB_IOLET_VELOCITY) {
-                    const double W = d->site_weight ? d->site_weight[s] : 1.0;
-                    const double ce = lat.c[i][0] * io.direction[0] + lat.c[i][1] * io.direction[1] +
-                                      lat.c[i][2] * io.direction[2];
-                    coef = 6.0 * lat.w[i] * ce * W;
-                }
-                gcoef.push_back((float)coef);
-            }
-        }
-    }
-    h->nghost = (int64_t)gsite.size();
-    if (n + h->nghost >= ((int64_t)1 << 30)) {
-        delete h;
-        return fail(HEMELB_EINVAL, "sites + iolet links must stay below 2^30");
-    }
-    h->slots = ((n + h->nghost + hlb::kTile - 1) / hlb::kTile) * hlb::kTile;
-    if (h->slots == 0) h->slots = hlb::kTile;
-    h->ttiles = (n + hlb::kTile - 1) / hlb::kTile;
-    if (h->ttiles == 0) h->ttiles = 1;
-
-    // internal pull table [tile][q-1][64]: fluid -> Morton index of the upstream
-    // site; wall -> bit 31 set (read the opposite direction of the same site) with
-    // the interpolated-wall fraction in units of 2^-15 in the low bits (0: halfway);
-    // iolet -> ghost slot n + l
-    std::vector<int32_t> tbl((size_t)h->ttiles * (q - 1) * hlb::kTile, 0);
-    {
-        std::vector<int64_t> gbase(n + 1, 0);
-        for (int64_t l = 0; l < h->nghost; ++l) gbase[gsite[l] + 1]++;
-        for (int64_t m = 0; m < n; ++m) gbase[m + 1] += gbase[m];
-        for (int64_t m = 0; m < n; ++m) {
-            const int64_t s = order[m];
-            int64_t g = gbase[m];
-            for (int i = 1; i < q; ++i) {
-                const int32_t v = d->nbr[s * q + i];
-                uint32_t e;
-                if (v >= 0)
-                    e = (uint32_t)inv[v];
-                else if (v == HEMELB_LINK_WALL)
-                    e = 0x80000000u | (d->wall_q ? wall_code(d->wall_q[s * q + i]) : 0u);
-                else
-                    e = (uint32_t)(n + (g++));
-                const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
-                                  (size_t)(m % hlb::kTile);
-                tbl[at] = (int32_t)e;
-            }
-        }
-    }
-
-    // wall normals [3][n] in Morton order
-    std::vector<float> nrm((size_t)3 * n, 0.f);
-    for (int64_t m = 0; m < n; ++m) {
-        const int64_t s = order[m];
-        double v[3] = {0, 0, 0};
-        if (d->wall_normal) {
-            for (int a = 0; a < 3; ++a) v[a] = d->wall_normal[3 * s + a];
-        } else {
-            for (int i = 1; i < q; ++i)
-                if (d->nbr[s * q + i] == HEMELB_LINK_WALL)
-                    for (int a = 0; a < 3; ++a) v[a] += lat.c[i][a];
-        }
-        const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (nn > 0)
-            for (int a = 0; a < 3; ++a) nrm[(size_t)a * n + m] = (float)(v[a] / nn);
-    }
-
-    // iolet descriptors and harmonics
-    std::vector<hlb::DevIolet> dio(d->n_iolets);
-    std::vector<double> harm;
-    for (int k = 0; k < d->n_iolets; ++k) {
-        const hemelb_iolet_t& io = d->iolets[k];
-        dio[k].kind = io.kind == HEMELB_IOLET_PRESSURE ? 0 : 1;
-        dio[k].n_harm = io.n_harm;
-        dio[k].harm_off = (int32_t)harm.size();
-        dio[k].pad = 0;
-        dio[k].mean = io.mean;
-        dio[k].period = io.n_harm > 0 ? io.period : 1.0;
-        for (int hh = 0; hh < io.n_harm; ++hh) harm.push_back(io.cos_k[hh]);
-        for (int hh = 0; hh < io.n_harm; ++hh) harm.push_back(io.sin_k[hh]);
-    }
-
-    std::vector<int32_t> perm;
-    if (d->coords) perm = order;
+    h->nghost = P.nghost;
+    h->slots = P.slots;
+    h->ttiles = P.ttiles;
+    h->addressing = P.addressing;
+    h->addr_bytes = P.addr_bytes;
     h->has_normal.assign(n, 0);
     for (int64_t m = 0; m < n; ++m)
-        h->has_normal[m] = (nrm[m] != 0.f || nrm[(size_t)n + m] != 0.f || nrm[2 * (size_t)n + m] != 0.f);
+        h->has_normal[m] = (P.nrm[m] != 0.f || P.nrm[(size_t)n + m] != 0.f ||
+                            P.nrm[2 * (size_t)n + m] != 0.f);
     for (int k = 0; k < d->n_iolets; ++k) {
         const hemelb_iolet_t& io = d->iolets[k];
-        hemelb_lb::HostIolet hi{io.kind, io.n_harm, dio[k].harm_off,
+        hemelb_lb::HostIolet hi{io.kind, io.n_harm, P.dio[k].harm_off,
                                 {io.direction[0], io.direction[1], io.direction[2]}};
         h->h_iolets.push_back(hi);
     }
-    h->h_harm = harm;
+    h->h_harm = P.harm;
     h->n_iolets = d->n_iolets;
-    std::vector<float> alpha;
-    if (d->alpha) {
-        alpha.resize(n);
-        for (int64_t m = 0; m < n; ++m) alpha[m] = d->alpha[order[m]];
-    }
 
 #define TRY(x)              \
     do {                    \
@@ -704,66 +1139,34 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         h->A[b] = p;
         h->device_bytes += (int64_t)popbytes;
     }
-    // compact form: 16-bit codes against a per-tile list of source tiles
-    {
-        bool compact = true;
-        if (const char* e = getenv("HEMELB_TABLE")) compact = atoi(e) != 32;
-        std::vector<uint16_t> t16;
-        std::vector<int32_t> toff, tlist;
-        if (compact) {
-            t16.assign(tbl.size(), 0);
-            toff.assign((size_t)h->ttiles + 1, 0);
-            std::vector<int32_t> tiles;
-            for (int64_t T = 0; T < h->ttiles && compact; ++T) {
-                tiles.clear();
-                const size_t base = (size_t)T * (q - 1) * hlb::kTile;
-                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
-                    const int32_t v = tbl[base + e];
-                    if (v >= 0) tiles.push_back(v >> hlb::kTileShift);
-                }
-                std::sort(tiles.begin(), tiles.end());
-                tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
-                if (tiles.size() > 2 * (size_t)hlb::kTile) {
-                    compact = false;
-                    break;
-                }
-                toff[T] = (int32_t)tlist.size();
-                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
-                    const int32_t v = tbl[base + e];
-                    uint16_t c;
-                    if (v < 0) {
-                        c = (uint16_t)(0x8000u | ((uint32_t)v & 0x7fffu));
-                    } else {
-                        const int32_t slot = (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
-                                                                        v >> hlb::kTileShift) -
-                                                       tiles.begin());
-                        c = (uint16_t)((slot << hlb::kTileShift) | (v & (hlb::kTile - 1)));
-                    }
-                    t16[base + e] = c;
-                }
-                tlist.insert(tlist.end(), tiles.begin(), tiles.end());
-            }
-            toff[h->ttiles] = (int32_t)tlist.size();
-        }
-        if (compact) {
-            TRY(dev_upload(h, &h->t16, t16, "compact table"));
-            TRY(dev_upload(h, &h->toff, toff, "table tile offsets"));
-            if (tlist.empty()) tlist.push_back(0);
-            TRY(dev_upload(h, &h->tlist, tlist, "table tile lists"));
-            h->tlist_len = (int64_t)tlist.size();
-        } else {
-            TRY(dev_upload(h, &h->tbl, tbl, "neighbour table"));
-        }
+    if (P.addressing == HEMELB_ADDR_BLOCKS) {
+        h->nfluid = P.bp.nfluid;
+        h->nblocks = (int32_t)P.bp.rec.size();
+        TRY(dev_upload(h, &h->brec, P.bp.rec, "block records"));
+        TRY(dev_upload(h, &h->gmask, P.bp.gmask, "ghost masks"));
+        TRY(dev_upload(h, &h->bnbr, P.bp.nbr, "neighbour blocks"));
+        TRY(dev_upload(h, &h->tblock, P.bp.tblock, "tile blocks"));
+        TRY(dev_upload(h, &h->g_slot, P.bp.gslot, "ghost slots"));
+        TRY(dev_upload(h, &h->gblob, P.bp.blob, "staged block records"));
+        TRY(dev_upload(h, &h->grp, P.bp.grp, "staged block groups"));
+        h->blob_words = (int64_t)P.bp.blob.size();
+    } else if (P.addressing == HEMELB_ADDR_TABLE16) {
+        TRY(dev_upload(h, &h->t16, P.t16, "compact table"));
+        TRY(dev_upload(h, &h->toff, P.toff, "table tile offsets"));
+        TRY(dev_upload(h, &h->tlist, P.tlist, "table tile lists"));
+        h->tlist_len = (int64_t)P.tlist.size();
+    } else {
+        TRY(dev_upload(h, &h->tbl, P.tbl, "neighbour table"));
     }
-    TRY(dev_upload(h, &h->g_site, gsite, "ghost sites"));
-    TRY(dev_upload(h, &h->g_dir, gdir, "ghost dirs"));
-    TRY(dev_upload(h, &h->g_iolet, giol, "ghost iolets"));
-    TRY(dev_upload(h, &h->g_coef, gcoef, "ghost coefs"));
-    TRY(dev_upload(h, &h->d_iolets, dio, "iolets"));
-    TRY(dev_upload(h, &h->d_harm, harm, "harmonics"));
-    TRY(dev_upload(h, &h->perm, perm, "permutation"));
-    TRY(dev_upload(h, &h->normal, nrm, "normals"));
-    TRY(dev_upload(h, &h->alpha, alpha, "alpha"));
+    TRY(dev_upload(h, &h->g_site, P.gsite, "ghost sites"));
+    TRY(dev_upload(h, &h->g_dir, P.gdir, "ghost dirs"));
+    TRY(dev_upload(h, &h->g_iolet, P.giol, "ghost iolets"));
+    TRY(dev_upload(h, &h->g_coef, P.gcoef, "ghost coefs"));
+    TRY(dev_upload(h, &h->d_iolets, P.dio, "iolets"));
+    TRY(dev_upload(h, &h->d_harm, P.harm, "harmonics"));
+    TRY(dev_upload(h, &h->perm, P.perm, "permutation"));
+    TRY(dev_upload(h, &h->normal, P.nrm, "normals"));
+    TRY(dev_upload(h, &h->alpha, P.alpha, "alpha"));
     h->nparts = hlb::totals_parts(n);
     TRY(dev_alloc(h, &h->partial, (size_t)h->nparts * 4, "partials"));
     TRY(dev_alloc(h, &h->tot, 4, "totals"));
@@ -790,10 +1193,10 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         return hip_fail(e, "create sync");
     }
 #undef TRY
-    h->order = std::move(order);
-    h->h_gsite = std::move(gsite);
-    h->h_gdir = std::move(gdir);
-    h->h_giol = std::move(giol);
+    h->order = std::move(P.order);
+    h->h_gsite = std::move(P.gsite);
+    h->h_gdir = std::move(P.gdir);
+    h->h_giol = std::move(P.giol);
     *out = h;
     return HEMELB_OK;
 }
@@ -911,6 +1314,7 @@ int hemelb_lb_info(hemelb_lb_t h, hemelb_lb_info_t* info) {
     info->storage = h->storage;
     info->bytes_per_update = h->bytes_per_update();
     info->device_bytes = h->device_bytes;
+    info->addressing = h->addressing;
     return HEMELB_OK;
 }
 

@@ -43,7 +43,7 @@ namespace hlb {
 #define HLB_SC_BLOCK 256
 #endif
 constexpr int kScBlock = HLB_SC_BLOCK;
-static_assert(kScBlock % kTile == 0, "block must hold whole tiles");
+static_assert(kScBlock == 4 * kTile, "a workgroup covers one group of four tiles");
 
 template <class T>
 __device__ inline void st_pop(T* p, T v) {
@@ -84,7 +84,7 @@ __device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const flo
 #endif
 
 // Pull, collide and store one site whose links are decoded in j.
-template <int Q, int ST, bool SC, bool BRINK>
+template <int Q, int ST, bool SC, bool BRINK, bool BFL>
 __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
                                    typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
                                    const float* __restrict__ alpha, const Ghosts& G,
@@ -99,7 +99,7 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
         link_src(i, j[i], s, dir, site);
         d[i] = C::dec(i, src[tix<Q>(dir, site)]);
     }
-    apply_bfl<Q, ST, SC>(src, s, n, j, d);
+    if constexpr (BFL) apply_bfl<Q, ST, SC>(src, s, n, j, d);
 
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -122,22 +122,39 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
         vs[i] = C::dec(i, e);
     }
 #if HLB_FUSE_GHOSTS
-    // ghost links of a site occupy consecutive slots in direction order
-    uint32_t mask = 0;
-    int32_t first = 0x7fffffff;
+    // The iolet links of a site are consecutive in the link list, in direction
+    // order.  With one slot per link (table encodings) the first one is the
+    // smallest ghost slot the site pulls from; with shared ghost cells (block
+    // addressing) it is found by a binary search of the list.
+    int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-        if (j[i] >= n) {
-            mask |= 1u << i;
-            first = min(first, j[i]);
+    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+    if (top >= n) {
+        uint32_t mask = 0;
+        int32_t first = 0x7fffffff;
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (j[i] >= n) {
+                mask |= 1u << i;
+                first = min(first, j[i]);
+            }
+        int64_t l = first - n;
+        if (G.slot) {
+            int64_t lo = 0, hi = G.count;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (G.site[mid] < s)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            l = lo;
         }
-    if (mask) {
-        int32_t slot = first;
 #pragma unroll
         for (int i = 1; i < Q; ++i)
             if (mask & (1u << i)) {
-                dst[tix<Q>(i, slot)] = C::enc(i, ghost_value<Q>(G, slot - n, i, vs, t_next));
-                ++slot;
+                dst[tix<Q>(i, ghost_slot(G, n, l))] = C::enc(i, ghost_value<Q>(G, l, i, vs, t_next));
+                ++l;
             }
     }
 #else
@@ -159,46 +176,21 @@ __device__ inline int32_t xcd_block(int32_t b, int32_t xcd_group) {
     return b;
 }
 
-// HLB_PERSIST: a fixed grid whose wavefronts walk the tiles (stride = number of
-// wavefronts), loading the next tile's link codes before gathering the current one.
-#ifndef HLB_PERSIST
-#define HLB_PERSIST 0
-#endif
-
-template <int Q, int ST, bool SC, bool BRINK>
+template <int Q, int ST, bool SC, bool BRINK, bool BFL>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha,
     Ghosts G, int64_t t_next) {
-#if HLB_PERSIST
-    constexpr int kWaves = kScBlock / kTile;
-    const int32_t ntiles = (n + kTile - 1) >> kTileShift;
-    const int32_t stride = (int32_t)gridDim.x * kWaves;
-    const int32_t lane = (int32_t)(threadIdx.x & (kTile - 1));
-    int32_t T = xcd_block((int32_t)blockIdx.x, xcd_group) * kWaves + (int32_t)(threadIdx.x >> kTileShift);
-    if (T >= ntiles) return;
-    uint32_t c[Q];
-    int32_t e0, e1;
-    load_codes<Q, HLB_NT_TABLE != 0>(tb, T * kTile + lane, c, e0, e1);
-    for (;;) {
-        const int32_t s = T * kTile + lane;
-        int32_t j[Q];
-        decode_codes<Q>(tb, s, c, e0, e1, j);
-        const int32_t Tn = T + stride;
-        if (Tn < ntiles) load_codes<Q, HLB_NT_TABLE != 0>(tb, Tn * kTile + lane, c, e0, e1);
-        if (s < n) site_update<Q, ST, SC, BRINK>(src, dst, n, omega, alpha, G, t_next, s, j);
-        if (Tn >= ntiles) break;
-        T = Tn;
-    }
-#else
-    const int32_t s = xcd_block((int32_t)blockIdx.x, xcd_group) * kScBlock + (int32_t)threadIdx.x;
-    if ((s & ~(kTile - 1)) >= n) return;  // the wavefront's whole tile lies past the end
-    // all table loads, then all population gathers, before any arithmetic
+    __shared__ StageLds lds;
+    const int32_t g = xcd_block((int32_t)blockIdx.x, xcd_group);
+    if (g * kScBlock >= n) return;  // the whole workgroup lies past the end
+    const int32_t s = g * kScBlock + (int32_t)threadIdx.x;
+    const bool live = (s & ~(kTile - 1)) < n;  // the wavefront's tile has sites
+    // all link decoding, then all population gathers, before any arithmetic
     int32_t j[Q];
-    links_wave<Q, HLB_NT_TABLE != 0>(tb, s, j);
-    if (s >= n) return;
-    site_update<Q, ST, SC, BRINK>(src, dst, n, omega, alpha, G, t_next, s, j);
-#endif
+    links_group<Q, HLB_NT_TABLE != 0>(tb, g, s, live, lds, j);
+    if (!live || s >= n) return;
+    site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,7 +211,6 @@ template <int Q, int ST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __restrict__ A,
                                                         Ghosts G, int32_t n, int64_t t) {
     using C = Codec<Q, ST, SC>;
-    using Lt = Lat<Q>;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= G.count) return;
     const int32_t s = G.site[l];
@@ -229,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(typename Store<ST>::T* __
     float vs[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) vs[k] = C::dec(k, A[tix<Q>(k, s)]);
-    A[tix<Q>(i, n + (int32_t)l)] = C::enc(i, ghost_value<Q>(G, l, i, vs, t));
+    A[tix<Q>(i, ghost_slot(G, n, l))] = C::enc(i, ghost_value<Q>(G, l, i, vs, t));
 }
 
 // ---------------------------------------------------------------------------
@@ -243,11 +234,14 @@ __global__ __launch_bounds__(kBlock) void k_observables(
     float* __restrict__ wss) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
-    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-    if ((s & ~(kTile - 1)) >= n) return;
+    static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
+    __shared__ StageLds lds;
+    const int32_t g = blockIdx.x;
+    const int32_t s = g * kBlock + threadIdx.x;
+    const bool live = (s & ~(kTile - 1)) < n;
     int32_t j[Q];
-    if (streamed) links_wave<Q, false>(tb, s, j);
-    if (s >= n) return;
+    if (streamed) links_group<Q, false>(tb, g, s, live, lds, j);
+    if (!live || s >= n) return;
     float d[Q];
     d[0] = C::dec(0, A[tix<Q>(0, s)]);
 #pragma unroll
@@ -436,32 +430,23 @@ hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* s
                                  hipStream_t s) {
     if (L.n == 0) return hipSuccess;
     int64_t nb = (L.n + kScBlock - 1) / kScBlock;
-#if HLB_PERSIST
-    // enough resident wavefronts to fill every CU, no more than one tile each
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            ncu <= 0)
-            ncu = 256;
-    }
-    nb = std::min<int64_t>(nb, (int64_t)ncu * HLB_PERSIST);
-#endif
     const int32_t per = xcd_group > 0 ? xcd_group : 0;
     int64_t grid = nb;
     if (per > 0) grid = ((nb + 8 * per - 1) / (8 * per)) * (8 * per);
     return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
+        auto go = [&](auto kernel, const float* a) {
+            kernel<<<(unsigned)grid, kScBlock, 0, s>>>(static_cast<const T*>(src),
+                                                       static_cast<T*>(dst), L.tb, (int32_t)L.n,
+                                                       per, omega, a, G, t_next);
+        };
         if (alpha)
-            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true><<<(unsigned)grid, kScBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, per, omega,
-                alpha, G, t_next);
+            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, true>, alpha)
+                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, false>, alpha);
         else
-            k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false><<<(unsigned)grid, kScBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, per, omega,
-                nullptr, G, t_next);
+            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, true>, nullptr)
+                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, false>, nullptr);
         return hipGetLastError();
     });
 }

@@ -20,19 +20,67 @@ struct DevIolet {
     double period;
 };
 
-// Neighbour table, [ceil(n/64)][q-1][64].  Decoded, a link names the source
-// site (>= 0), the site itself with bit 31 set for a bounce-back wall link, or
-// n + l for ghost slot l.  Two encodings:
-//  * t32: that int32 value directly;
-//  * t16 (compact): bit 15 = wall; bits 6..14 = slot in the tile's list of source
-//    tiles tlist[toff[T] .. toff[T+1]) (at most 128 entries); bits 0..5 = lane
-//    within the source tile.  Source site = tlist[toff[T] + slot] * 64 + lane.
+// One 4x4x4 block of the lattice in block addressing.  Positions inside a block
+// are 6-bit Morton codes p (bits x0 y0 z0 x1 y1 z1), the order of the sites.
+struct BlockRec {
+    uint32_t mask_lo, mask_hi;  // fluid positions
+    int32_t off;                // site index of the block's first fluid site
+    int32_t goff;               // ghost index of its first ghost cell, -1: none
+};
+
+// How a site's links are found.  Decoded, a link names the source site (>= 0),
+// bit 31 set for a wall link (the kernel then reads the opposite population of
+// the site itself; the low 15 bits hold the interpolated-wall fraction, 0 for
+// halfway bounce-back), or a ghost slot >= n holding the incoming population of
+// an iolet link.  Three encodings:
+//  * t32: neighbour table [ceil(n/64)][q-1][64] of those int32 values;
+//  * t16 (compact): the same table in 16 bits: bit 15 = wall (bits 0..14 the
+//    fraction); else bits 6..14 = slot in the tile's list of source tiles
+//    tlist[toff[T] .. toff[T+1]) (at most 128 entries) and bits 0..5 = lane
+//    within the source tile, source site = tlist[toff[T] + slot] * 64 + lane;
+//  * brec (two-level block addressing, no per-link data): the lattice is cut into
+//    4x4x4 blocks; a block record holds its fluid mask and first site index, so
+//    the site at position p of block b is brec[b].off + popcount(mask below p).
+//    bnbr[b][27] lists the ids of the 27 blocks around block b (index
+//    (dx+1) + 3 (dy+1) + 9 (dz+1), -1 where no block exists, 13 = b itself);
+//    tblock[T] is the block of the first site of tile T.  Positions past an iolet
+//    plane that some link pulls from are ghost cells: gmask[b] marks them and the
+//    g-th cell (block order, then position) holds its populations in slot n + g.
+//    Blocks nfluid.. hold ghost cells only.  A position that is neither fluid nor
+//    a ghost cell is a wall (halfway bounce-back).
+//
+//    For a fast decode every group of four tiles (256 sites, one workgroup) has a
+//    staged copy of the records it needs, loaded into LDS with one coalesced read
+//    per workgroup: grp[2g] = offset of group g's blob in 16-byte units, grp[2g+1]
+//    = nown | nrec << 16 (nown = 0: the group uses the global records).  The blob
+//    holds nown rows of kRowBytes bytes (the group's own blocks, consecutive ids
+//    from the block of its first site; row k, byte d = index into the blob's
+//    records of neighbour d of own block k; where no block exists it names an
+//    empty record (no fluid, no ghost cells)), padded to 16 bytes,
+//    then nrec BlockRecs whose first nown are the own blocks in order; in these
+//    copies goff holds the block's id when it has ghost cells (-1 otherwise).
 struct Table {
     const int32_t* t32;
     const uint16_t* t16;
     const int32_t* toff;
     const int32_t* tlist;
+    const BlockRec* brec;
+    const uint64_t* gmask;
+    const int32_t* bnbr;
+    const int32_t* tblock;
+    const uint4* gblob;
+    const int32_t* grp;
+    int32_t nfluid;  // blocks holding fluid sites
+    int32_t nblocks;
+    int32_t n;       // fluid sites (the first ghost slot)
 };
+
+// capacity of a group's staged blob (groups beyond it use the global records)
+constexpr int kRowBytes = 28;
+constexpr int kStageRows = 24;
+constexpr int kStageRowChunks = (kStageRows * kRowBytes + 15) / 16;
+constexpr int kStageRecs = 160;
+constexpr int kStageChunks = kStageRowChunks + kStageRecs;  // <= threads per workgroup
 
 // Layout of one handle's device data, shared by all launches.  Populations are
 // stored [slots/64][q][64] (sites, then ghost slots, Morton order).
@@ -43,10 +91,16 @@ struct Layout {
     int64_t n;      // fluid sites
     int64_t slots;  // site + ghost slots per direction, a multiple of 64
     Table tb;
+    bool bfl;       // some wall links carry an interpolated-wall fraction
 };
 
+// Iolet links, sorted by site then direction.  Link l's incoming population lives
+// in direction dir[l] of slot slot[l] (null: slot n + l, one slot per link, the
+// table encodings; block addressing shares one ghost cell among the links that
+// pull from the same position).
 struct Ghosts {
     int64_t count;
+    const int32_t* slot;
     const int32_t* site;   // Morton site index of each iolet link
     const uint8_t* dir;    // direction of the link
     const uint8_t* iolet;  // iolet id

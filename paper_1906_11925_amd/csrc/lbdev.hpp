@@ -124,22 +124,242 @@ __device__ inline void decode_codes(const Table& tb, int32_t s, const uint32_t (
     }
 }
 
+// ---- two-level block addressing -------------------------------------------
+__device__ inline uint64_t block_mask(const BlockRec& r) {
+    return ((uint64_t)r.mask_hi << 32) | (uint64_t)r.mask_lo;
+}
+
+// position of the set bit of rank r (counted from 0) of m; the result stays in
+// [0, 63] for any m and r
+__device__ inline int select_bit(uint64_t m, int r) {
+    uint32_t x = (uint32_t)m;
+    int p = 0;
+    int c = __popc(x);
+    if (r >= c) {
+        r -= c;
+        x = (uint32_t)(m >> 32);
+        p = 32;
+    }
+    c = __popc(x & 0xffffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 16;
+        p += 16;
+    }
+    c = __popc(x & 0xffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 8;
+        p += 8;
+    }
+    c = __popc(x & 0xfu);
+    if (r >= c) {
+        r -= c;
+        x >>= 4;
+        p += 4;
+    }
+    c = __popc(x & 0x3u);
+    if (r >= c) {
+        r -= c;
+        x >>= 2;
+        p += 2;
+    }
+    if (r >= (int)(x & 1u)) p += 1;
+    return p;
+}
+
+// 6-bit Morton position of local coordinates (x, y, z) in [0, 4)^3
+__device__ inline int block_pos(int x, int y, int z) {
+    return (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((x & 2) << 2) | ((y & 2) << 3) |
+           ((z & 2) << 4);
+}
+
+// Links j[1..Q-1] of the site at local coordinates (bx, by, bz) of block bl.
+template <int Q>
+__device__ inline void block_links(const Table& tb, int32_t bl, int bx, int by, int bz,
+                                   int32_t (&j)[Q]) {
+    using Lt = Lat<Q>;
+    const int32_t* nb = tb.bnbr + (int64_t)bl * 27;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int ux = bx - Lt::cx[i], uy = by - Lt::cy[i], uz = bz - Lt::cz[i];  // in [-1, 4]
+        const int d = ((ux >> 2) + 1) + 3 * ((uy >> 2) + 1) + 9 * ((uz >> 2) + 1);
+        const int32_t b2 = nb[d];
+        int32_t v = (int32_t)0x80000000u;  // wall
+        if (b2 >= 0) {
+            const BlockRec r = tb.brec[b2];
+            const uint64_t m = block_mask(r);
+            const int p = block_pos(ux & 3, uy & 3, uz & 3);
+            const uint64_t below = (1ull << p) - 1ull;
+            if ((m >> p) & 1ull) {
+                v = r.off + __popcll(m & below);
+            } else if (r.goff >= 0) {
+                const uint64_t g = tb.gmask[b2];
+                if ((g >> p) & 1ull) v = tb.n + r.goff + __popcll(g & below);
+            }
+        }
+        j[i] = v;
+    }
+}
+
+// the site's block bl (given a first guess b0 <= bl) and its local coordinates
+__device__ inline void block_site(const Table& tb, int32_t s, int32_t bl, int& bx, int& by,
+                                  int& bz) {
+    const BlockRec r = tb.brec[bl];
+    const int p = select_bit(block_mask(r), s - r.off);
+    bx = (p & 1) | ((p >> 2) & 2);
+    by = ((p >> 1) & 1) | ((p >> 3) & 2);
+    bz = ((p >> 2) & 1) | ((p >> 4) & 2);
+}
+
+// Wave form: the blocks that the tile's sites fall into are found with
+// wave-uniform loads of their first-site offsets.
+template <int Q>
+__device__ inline void links_blocks_wave(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+    const int32_t T = __builtin_amdgcn_readfirstlane(s >> kTileShift);
+    const int32_t end = (T + 1) << kTileShift;
+    const int32_t b0 = tb.tblock[T];
+    int32_t bl = b0;
+    for (int32_t b = b0 + 1; b < tb.nfluid; ++b) {
+        const int32_t o = tb.brec[b].off;
+        if (o >= end) break;
+        if (s >= o) bl = b;
+    }
+    int bx, by, bz;
+    block_site(tb, s, bl, bx, by, bz);
+    block_links<Q>(tb, bl, bx, by, bz, j);
+}
+
+// LDS of one workgroup for the staged block records
+struct StageLds {
+    uint4 chunk[kStageChunks];
+};
+
+// Links of the sites of one 256-thread workgroup (group g = four consecutive
+// tiles) from the group's staged block records.  Every thread of the workgroup
+// calls it (it holds a barrier); `live`: the thread's wavefront has sites.
+template <int Q>
+__device__ inline void links_blocks_group(const Table& tb, int32_t g, int32_t s, bool live,
+                                          StageLds& lds, int32_t (&j)[Q]) {
+    using Lt = Lat<Q>;
+    const int32_t off = tb.grp[2 * g];
+    const int32_t cnt = tb.grp[2 * g + 1];
+    const int nown = cnt & 0xffff, nrec = cnt >> 16;
+    if (nown == 0) {  // the group's records did not fit: global records
+        if (live) links_blocks_wave<Q>(tb, s, j);
+        return;
+    }
+    const int row_chunks = (nown * kRowBytes + 15) >> 4;
+    const int t = (int)threadIdx.x;
+    if (t < row_chunks)
+        lds.chunk[t] = tb.gblob[off + t];
+    else if (t < row_chunks + nrec)
+        lds.chunk[kStageRowChunks + t - row_chunks] = tb.gblob[off + t];
+    __syncthreads();
+    const uint8_t* rows = reinterpret_cast<const uint8_t*>(lds.chunk);
+    const BlockRec* recs = reinterpret_cast<const BlockRec*>(lds.chunk + kStageRowChunks);
+    // own block: the last one whose first site is at or before s (offsets ascend;
+    // only blocks starting inside this wavefront's tile can change the answer)
+    const int32_t last = __builtin_amdgcn_readfirstlane(s | (kTile - 1));
+    int k = 0;
+    for (int q = 1; q < nown; ++q) {
+        const int32_t o = recs[q].off;
+        if (o > last) break;
+        if (s >= o) k = q;
+    }
+    const BlockRec own = recs[k];
+    const int p = select_bit(block_mask(own), s - own.off);
+    const int bx = (p & 1) | ((p >> 2) & 2);
+    const int by = ((p >> 1) & 1) | ((p >> 3) & 2);
+    const int bz = ((p >> 2) & 1) | ((p >> 4) & 2);
+    const uint8_t* row = rows + k * kRowBytes;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        // upstream point in block coordinates: neighbour block d and position pp
+        const int ux = bx - Lt::cx[i], uy = by - Lt::cy[i], uz = bz - Lt::cz[i];  // in [-1, 4]
+        const int d = ((ux >> 2) + 1) + 3 * ((uy >> 2) + 1) + 9 * ((uz >> 2) + 1);
+        const int pp = block_pos(ux & 3, uy & 3, uz & 3);
+        const BlockRec r = recs[row[d]];  // a missing block reads the staged empty record
+        const uint32_t sh = (uint32_t)pp & 31u;
+        const bool upper = pp >= 32;
+        const uint32_t w = upper ? r.mask_hi : r.mask_lo;
+        const int rank = __popc(w & ((1u << sh) - 1u)) + (upper ? __popc(r.mask_lo) : 0);
+        const bool fluid = (w >> sh) & 1u;
+        int32_t v = fluid ? r.off + rank : (int32_t)0x80000000u;  // else wall...
+        if (!fluid && r.goff >= 0) {
+            // ...unless it is a ghost cell (rare: the staged copy names the block's
+            // id; its ghost mask and first ghost index stay in global memory)
+            const int32_t b2 = r.goff;
+            const uint64_t gm = tb.gmask[b2];
+            if ((gm >> pp) & 1ull)
+                v = tb.n + tb.brec[b2].goff + __popcll(gm & ((1ull << pp) - 1ull));
+        }
+        j[i] = v;
+    }
+}
+
+// Links of site s in a kernel whose 256-thread workgroups each cover one group g
+// of four consecutive tiles (s = 256 g + thread).  Every thread of the workgroup
+// calls it; `live`: the thread's wavefront has sites (the others only help stage).
+template <int Q, bool NT>
+__device__ inline void links_group(const Table& tb, int32_t g, int32_t s, bool live,
+                                   StageLds& lds, int32_t (&j)[Q]);
+
+// Wave form of the link decode (all lanes of a wavefront call it); block
+// addressing decodes from the global records here (see links_group).
 template <int Q, bool NT>
 __device__ inline void links_wave(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+    if (tb.brec) {
+        links_blocks_wave<Q>(tb, s, j);
+        return;
+    }
     uint32_t c[Q];
     int32_t e0, e1;
     load_codes<Q, NT>(tb, s, c, e0, e1);
     decode_codes<Q>(tb, s, c, e0, e1, j);
 }
 
-// One link of an arbitrary site (no lane exchange).
+template <int Q, bool NT>
+__device__ inline void links_group(const Table& tb, int32_t g, int32_t s, bool live,
+                                   StageLds& lds, int32_t (&j)[Q]) {
+    if (tb.grp) {
+        links_blocks_group<Q>(tb, g, s, live, lds, j);
+        return;
+    }
+    if (live) links_wave<Q, NT>(tb, s, j);
+}
+
+// All links of an arbitrary site (no lane exchange; any lane may call it).
 template <int Q>
-__device__ inline int32_t link_one(const Table& tb, int32_t s, int i) {
-    if (tb.t16 == nullptr) return tb.t32[tix<Q - 1>(i - 1, s)];
-    const uint32_t c = tb.t16[tix<Q - 1>(i - 1, s)];
-    if (c & 0x8000u) return (int32_t)(0x80000000u | (c & 0x7fffu));
-    const int32_t tile = tb.tlist[tb.toff[s >> kTileShift] + (int)((c >> kTileShift) & 0x1ffu)];
-    return (tile << kTileShift) | (int32_t)(c & (kTile - 1));
+__device__ inline void links_site(const Table& tb, int32_t s, int32_t (&j)[Q]) {
+    if (tb.brec) {
+        int32_t bl = tb.tblock[s >> kTileShift];
+        while (bl + 1 < tb.nfluid && tb.brec[bl + 1].off <= s) ++bl;
+        int bx, by, bz;
+        block_site(tb, s, bl, bx, by, bz);
+        block_links<Q>(tb, bl, bx, by, bz, j);
+        return;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (tb.t16 == nullptr) {
+            j[i] = tb.t32[tix<Q - 1>(i - 1, s)];
+            continue;
+        }
+        const uint32_t c = tb.t16[tix<Q - 1>(i - 1, s)];
+        if (c & 0x8000u) {
+            j[i] = (int32_t)(0x80000000u | (c & 0x7fffu));
+        } else {
+            const int32_t tile =
+                tb.tlist[tb.toff[s >> kTileShift] + (int)((c >> kTileShift) & 0x1ffu)];
+            j[i] = (tile << kTileShift) | (int32_t)(c & (kTile - 1));
+        }
+    }
+}
+
+// slot holding the incoming population of iolet link l
+__device__ inline int32_t ghost_slot(const Ghosts& G, int32_t n, int64_t l) {
+    return G.slot ? G.slot[l] : n + (int32_t)l;
 }
 
 // moments of FP32 deviations: drho = sum d, m = sum c d (constant-folded per lattice)

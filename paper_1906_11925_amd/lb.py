@@ -53,63 +53,104 @@ def _torch():
     return torch
 
 
+def _desc(nbr, tau, lattice=15, storage="f32", coords=None, iolets=(), site_weight=None,
+          wall_normal=None, alpha=None, stream_ptr=None, scale=True, wall_q=None,
+          addressing="auto"):
+    """(DescT, arrays it points into) for the arguments of `LB`."""
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    n = nbr.shape[0]
+    if nbr.ndim != 2 or nbr.shape[1] != lattice:
+        raise ValueError("nbr must be [N, lattice]")
+    if addressing not in L.ADDRESSING:
+        raise ValueError(f"addressing must be one of {sorted(L.ADDRESSING)}")
+    keep = [nbr]
+    io_arr = (L.IoletT * max(1, len(iolets)))()
+    keep.append(io_arr)
+    for k, io in enumerate(iolets):
+        cos = np.ascontiguousarray(getattr(io, "cos", ()), dtype=np.float64)
+        sin = np.ascontiguousarray(getattr(io, "sin", ()), dtype=np.float64)
+        if cos.shape != sin.shape:
+            raise ValueError("cos and sin harmonics must have the same length")
+        keep += [cos, sin]
+        io_arr[k].kind = L.IOLET_PRESSURE if io.kind == "pressure" else L.IOLET_VELOCITY
+        for a in range(3):
+            io_arr[k].direction[a] = float(io.direction[a])
+        io_arr[k].mean = float(io.mean)
+        io_arr[k].n_harm = int(cos.size)
+        io_arr[k].cos_k = _ptr(cos, L.c_double) if cos.size else None
+        io_arr[k].sin_k = _ptr(sin, L.c_double) if sin.size else None
+        io_arr[k].period = float(getattr(io, "period", 1.0))
+    d = L.DescT()
+    d.lattice = lattice
+    d.storage = _STORE[storage]
+    d.flags = (0 if scale else L.FLAG_NO_SCALE) | L.ADDRESSING[addressing]
+    d.n_sites = n
+    if coords is not None:
+        coords = np.ascontiguousarray(coords, dtype=np.int32)
+        keep.append(coords)
+        d.coords = _ptr(coords, L.c_int32)
+    d.nbr = _ptr(nbr, L.c_int32)
+    d.tau = float(tau)
+    d.n_iolets = len(iolets)
+    d.iolets = io_arr
+    if wall_q is not None:
+        wall_q = np.nan_to_num(np.asarray(wall_q, dtype=np.float32), nan=0.5)
+    for name, arr, ct, dt in (("site_weight", site_weight, L.c_double, np.float64),
+                              ("wall_normal", wall_normal, L.c_float, np.float32),
+                              ("alpha", alpha, L.c_float, np.float32),
+                              ("wall_q", wall_q, L.c_float, np.float32)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=dt)
+            keep.append(a)
+            setattr(d, name, _ptr(a, ct))
+    d.stream = stream_ptr
+    return d, keep
+
+
+def _info_dict(i):
+    out = {f: getattr(i, f) for f, _ in L.InfoT._fields_}
+    out["addressing_name"] = L.ADDR_NAMES.get(out["addressing"], "?")
+    return out
+
+
+def plan(nbr, tau, **kw):
+    """Layout `LB(nbr, tau, **kw)` would build, from the host library alone (no
+    GPU needed): n_sites, n_ghosts, pitch, addressing, bytes_per_update and the
+    device bytes it would allocate."""
+    lib = L.load()
+    d, keep = _desc(nbr, tau, **kw)
+    i = L.InfoT()
+    L.check(lib.hemelb_lb_plan(ctypes.byref(d), ctypes.byref(i)))
+    del keep
+    return _info_dict(i)
+
+
+def plan_geometry(geom, lattice=15, storage="f32", tau=None, bfl=False, **kw):
+    """`plan` for a workloads.Geometry, with the arguments of LB.from_geometry."""
+    coords, nbr = links(geom.labels, geom.shape, geom.periodic, lattice)
+    if bfl:
+        kw["wall_q"] = geom.wall_fractions(lattice_vectors(lattice))
+    return plan(nbr, geom.tau if tau is None else tau, lattice=lattice, storage=storage,
+                coords=coords, iolets=list(geom.iolets), site_weight=geom.site_weight(), **kw)
+
+
 class LB:
     """One simulation handle on the current GPU (see include/hemelb_lb.h)."""
 
     def __init__(self, nbr, tau, lattice=15, storage="f32", coords=None, iolets=(),
                  site_weight=None, wall_normal=None, alpha=None, stream=None, scale=True,
-                 wall_q=None):
+                 wall_q=None, addressing="auto"):
         torch = _torch()
         self.lib = L.load()
-        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
-        n = nbr.shape[0]
-        if nbr.ndim != 2 or nbr.shape[1] != lattice:
-            raise ValueError("nbr must be [N, lattice]")
-        self.n, self.q, self.storage = n, lattice, storage
-        self.tau = float(tau)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        keep = []
-        io_arr = (L.IoletT * max(1, len(iolets)))()
-        for k, io in enumerate(iolets):
-            cos = np.ascontiguousarray(getattr(io, "cos", ()), dtype=np.float64)
-            sin = np.ascontiguousarray(getattr(io, "sin", ()), dtype=np.float64)
-            if cos.shape != sin.shape:
-                raise ValueError("cos and sin harmonics must have the same length")
-            keep += [cos, sin]
-            io_arr[k].kind = L.IOLET_PRESSURE if io.kind == "pressure" else L.IOLET_VELOCITY
-            for a in range(3):
-                io_arr[k].direction[a] = float(io.direction[a])
-            io_arr[k].mean = float(io.mean)
-            io_arr[k].n_harm = int(cos.size)
-            io_arr[k].cos_k = _ptr(cos, L.c_double) if cos.size else None
-            io_arr[k].sin_k = _ptr(sin, L.c_double) if sin.size else None
-            io_arr[k].period = float(getattr(io, "period", 1.0))
-        d = L.DescT()
-        d.lattice = lattice
-        d.storage = _STORE[storage]
-        d.flags = 0 if scale else L.FLAG_NO_SCALE
-        d.n_sites = n
-        if coords is not None:
-            coords = np.ascontiguousarray(coords, dtype=np.int32)
-            keep.append(coords)
-            d.coords = _ptr(coords, L.c_int32)
-        d.nbr = _ptr(nbr, L.c_int32)
-        d.tau = self.tau
-        d.n_iolets = len(iolets)
-        d.iolets = io_arr
-        if wall_q is not None:
-            wall_q = np.nan_to_num(np.asarray(wall_q, dtype=np.float32), nan=0.5)
-        for name, arr, ct, dt in (("site_weight", site_weight, L.c_double, np.float64),
-                                  ("wall_normal", wall_normal, L.c_float, np.float32),
-                                  ("alpha", alpha, L.c_float, np.float32),
-                                  ("wall_q", wall_q, L.c_float, np.float32)):
-            if arr is not None:
-                a = np.ascontiguousarray(arr, dtype=dt)
-                keep.append(a)
-                setattr(d, name, _ptr(a, ct))
-        d.stream = ctypes.c_void_p(stream.cuda_stream)
+        d, keep = _desc(nbr, tau, lattice=lattice, storage=storage, coords=coords, iolets=iolets,
+                        site_weight=site_weight, wall_normal=wall_normal, alpha=alpha,
+                        stream_ptr=ctypes.c_void_p(stream.cuda_stream), scale=scale,
+                        wall_q=wall_q, addressing=addressing)
+        self.n, self.q, self.storage = d.n_sites, lattice, storage
+        self.tau = float(tau)
         h = ctypes.c_void_p()
         L.check(self.lib.hemelb_lb_create(ctypes.byref(h), ctypes.byref(d)))
         self.h = h
@@ -156,7 +197,7 @@ class LB:
     def info(self):
         i = L.InfoT()
         L.check(self.lib.hemelb_lb_info(self.h, ctypes.byref(i)))
-        return {f: getattr(i, f) for f, _ in L.InfoT._fields_}
+        return _info_dict(i)
 
     @property
     def time(self):

@@ -28,6 +28,10 @@ HEMELB_ECANCELLED = -6
 
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 FLAG_NO_SCALE = 1
+FLAG_BLOCKS, FLAG_TABLE16, FLAG_TABLE32 = 2, 4, 8
+ADDR_TABLE32, ADDR_TABLE16, ADDR_BLOCKS = 0, 1, 2
+ADDRESSING = {"auto": 0, "blocks": FLAG_BLOCKS, "table16": FLAG_TABLE16, "table32": FLAG_TABLE32}
+ADDR_NAMES = {ADDR_TABLE32: "table32", ADDR_TABLE16: "table16", ADDR_BLOCKS: "blocks"}
 IOLET_PRESSURE, IOLET_VELOCITY = 0, 1
 
 
@@ -48,7 +52,8 @@ class DescT(ctypes.Structure):
 class InfoT(ctypes.Structure):
     _fields_ = [("n_sites", c_int64), ("n_ghosts", c_int64), ("pitch", c_int64),
                 ("time", c_int64), ("lattice", c_int32), ("storage", c_int32),
-                ("bytes_per_update", c_double), ("device_bytes", c_int64)]
+                ("bytes_per_update", c_double), ("device_bytes", c_int64),
+                ("addressing", c_int32)]
 
 
 class ObjectiveT(ctypes.Structure):
@@ -81,6 +86,7 @@ _SIGS = {
     "hemelb_lb_get_deviations": (c_int32, [c_void_p, c_void_p]),
     "hemelb_lb_set_deviations": (c_int32, [c_void_p, c_void_p, c_int64]),
     "hemelb_lb_info": (c_int32, [c_void_p, P(InfoT)]),
+    "hemelb_lb_plan": (c_int32, [P(DescT), P(InfoT)]),
     "hemelb_lb_kernel_timing": (c_int32, [c_void_p, c_int64]),
     "hemelb_lb_kernel_time": (c_int32, [c_void_p, P(c_double), P(c_int64)]),
     "hemelb_copy_probe": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),

@@ -72,7 +72,9 @@ def test_reject_bad_tau(box, tau):
 def test_reject_bad_storage_and_flags(box):
     _, nbr = box
     assert _create(_desc(nbr, storage=7))[0] == L.HEMELB_EINVAL
-    assert _create(_desc(nbr, flags=8))[0] == L.HEMELB_EINVAL
+    assert _create(_desc(nbr, flags=16))[0] == L.HEMELB_EINVAL
+    rc, msg = _create(_desc(nbr, flags=L.FLAG_BLOCKS | L.FLAG_TABLE16))
+    assert rc == L.HEMELB_EINVAL and "at most one" in msg
 
 
 def test_reject_nonreciprocal_link(box):

@@ -66,9 +66,10 @@ def _problem(g, T, W, seed=4, amax=0.01, dome_fn=None, q=15, start_amp=0.0):
                 ahat=ahat, g0=g0, T=T, lattice=q, d0=d0)
 
 
-def _gpu_run(P, K):
+def _gpu_run(P, K, addressing="auto"):
     g, obj = P["g"], P["obj"]
-    lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32))
+    lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32),
+                          addressing=addressing)
     lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
     if P["d0"] is not None:
         lb.set_deviations(torch.from_numpy(P["d0"]), t=0)
@@ -118,6 +119,17 @@ def test_segmentation_is_exact(tiny):
     a = _gpu_run(tiny, 40)
     b = _gpu_run(tiny, 7)
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_addressing_modes_give_identical_gradients(tiny):
+    """Block addressing (shared ghost cells) and the explicit table drive the same
+    reverse steps: objective, flux and every gradient are bit-identical."""
+    _gpu()
+    a = _gpu_run(tiny, 7, "blocks")
+    b = _gpu_run(tiny, 7, "table16")
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    for x, y in zip(a[2:], b[2:]):
+        assert np.array_equal(x, y)
 
 
 def test_autograd_function(tiny):

@@ -412,23 +412,81 @@ def test_tree2048_one_step_sampled(tree2048, q):
     assert np.abs(gpu - ref).max() < fp32_tol(q, 1e-3)
 
 
-def test_compact_table_matches_int32_table(monkeypatch):
-    """The 16-bit table (codes against per-tile source lists) decodes to the same
-    links as the int32 table: identical bits after 30 steps, observables too."""
+def _tree_small():
+    return wl.tree(box=96, r0=6.0, root=(48.0, 48.0, 4.0), generations=3, seed=1)
+
+
+def _iolet_only_site():
+    around = [((x, y, z), 0) for x in range(-1, 4) for y in range(-1, 4) for z in range(-1, 4)
+              if (x, y, z) != (1, 1, 1) and max(abs(x - 1), abs(y - 1), abs(z - 1)) == 1]
+    return _lattice_box((3, 3, 3), [(1, 1, 1)], around, tau=0.8,
+                        iolets=[Iolet("pressure", mean=1.002)])
+
+
+ADDR = {"blocks": L.ADDR_BLOCKS, "table16": L.ADDR_TABLE16, "table32": L.ADDR_TABLE32}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("name", ["pipe", "aneurysm_half", "tree_small", "iolet_only_site"])
+def test_addressing_modes_are_bit_identical(name, q, storage):
+    """Block addressing, the 16-bit table and the int32 table find the same
+    upstream populations: identical bits after 30 steps from a random state
+    (pressure and Ladd iolets, walls), observables too.  Block addressing shares
+    one ghost cell among the links that pull from one position, so it needs no
+    more ghost slots, and it reads fewer addressing bytes."""
     _gpu()
-    g = wl.aneurysm(half=True)
-    runs = []
-    for mode in ("32", "16"):
-        monkeypatch.setenv("HEMELB_TABLE", mode)
-        lb = LB.from_geometry(g, storage="f16")
+    g = {"pipe": wl.pipe, "aneurysm_half": lambda: wl.aneurysm(half=True),
+         "tree_small": _tree_small, "iolet_only_site": _iolet_only_site}[name]()
+    d = torch.from_numpy(quantize(wl.random_deviations(q, g.n_sites, 3, 1e-3), q, storage))
+    runs = {}
+    for mode in ("blocks", "table16", "table32"):
+        lb = LB.from_geometry(g, lattice=q, storage=storage, addressing=mode)
+        info = lb.info()
+        assert info["addressing"] == ADDR[mode]
+        lb.set_deviations(d, t=5)
         lb.step(30)
-        runs.append((lb.get_state()[0], lb.observables(), lb.info()["bytes_per_update"]))
+        runs[mode] = (lb.get_state()[0], lb.observables(), info)
         lb.close()
-    assert torch.equal(runs[0][0], runs[1][0])
-    for x, y in zip(runs[0][1], runs[1][1]):
-        assert torch.equal(x, y)
-    assert runs[0][2] == 2 * 15 * 2 + 4 * 14
-    assert runs[1][2] < 2 * 15 * 2 + 2 * 14 + 4
+    for mode in ("table16", "table32"):
+        assert torch.equal(runs["blocks"][0], runs[mode][0])
+        for x, y in zip(runs["blocks"][1], runs[mode][1]):
+            assert torch.equal(x, y)
+    ib, i16, i32 = (runs[m][2] for m in ("blocks", "table16", "table32"))
+    assert ib["n_ghosts"] == i16["n_ghosts"] == i32["n_ghosts"]
+    assert ib["pitch"] <= i16["pitch"] == i32["pitch"]
+    pops = 2 * q * (4 if storage == "f32" else 2)
+    assert i32["bytes_per_update"] == pops + 4 * (q - 1)
+    if name != "iolet_only_site":  # per-tile and per-block terms dominate a 1-site lattice
+        assert i16["bytes_per_update"] < pops + 2 * (q - 1) + 4
+        assert ib["bytes_per_update"] < pops + 8
+
+
+def test_auto_addressing_prefers_blocks_and_falls_back():
+    """The default is block addressing for 16-bit storage (with coordinates and
+    halfway walls) and the 16-bit table for FP32; a periodic lattice (links that
+    wrap) and interpolated walls use the table; asking for blocks where they do not
+    apply is an error that names the reason."""
+    _gpu()
+    lb = LB.from_geometry(wl.pipe(), storage="f16")
+    assert lb.info()["addressing"] == L.ADDR_BLOCKS
+    lb.close()
+    lb = LB.from_geometry(wl.pipe())
+    assert lb.info()["addressing"] == L.ADDR_TABLE16
+    lb.close()
+    per = wl.periodic_box(5, 7, 6)
+    lb = LB.from_geometry(per, storage="f16")
+    assert lb.info()["addressing"] == L.ADDR_TABLE16
+    lb.close()
+    with pytest.raises(HemelbError) as ei:
+        LB.from_geometry(per, addressing="blocks")
+    assert ei.value.code == L.HEMELB_EINVAL and "block addressing" in str(ei.value)
+    with pytest.raises(HemelbError) as ei:
+        LB.from_geometry(wl.pipe(), addressing="blocks", bfl=True)
+    assert ei.value.code == L.HEMELB_EINVAL and "interpolated" in str(ei.value)
+    lb = LB.from_geometry(wl.pipe(), bfl=True, storage="f16")
+    assert lb.info()["addressing"] == L.ADDR_TABLE16
+    lb.close()
 
 
 def _lattice_box(shape, fluid_pts, iolet_pts=(), periodic=(False, False, False), tau=0.7,
