@@ -6,25 +6,31 @@
 //   Q(t) = sum over the outlet's iolet links (s, i) of A_t[opp(i)][s] - f_t[i][s].
 //
 // One reverse step t (given g = dJ/dA_{t+1}, FP32, same tiled layout as the
-// populations) is two kernels:
-//  * k_adj_scatter, one thread per site: re-gathers f_t from the taped A_t,
-//    applies the transposed collision Jacobian
+// populations) is one kernel, k_adj_scatter, one thread per site:
+//  * it re-gathers f_t from the taped A_t, applies the transposed collision
+//    Jacobian
 //      fhat_j = (1 - omega) g_j + omega (a + c_j . b),
 //      a = sum_i g_i dfeq_i/drho, b = sum_i g_i dfeq_i/dm  (Brinkman-aware),
 //    adds the wall-shear objective term, accumulates dJ/dalpha_s in FP64, and
 //    writes fhat_i to exactly the address the forward pull read f_i from (the
-//    upstream site, the site's own opposite population for a wall link, or the
-//    link's ghost slot).  Every population location is read by at most one link,
-//    so the push needs no atomics; the populations that leave through iolets are
-//    read by nobody and are set to zero here.
-//  * k_adj_iolet, one thread per site with iolet links: turns the adjoints that
-//    landed in ghost slots into their sources: the Ladd term sends its adjoint to
-//    the site's opposite population and (times its coefficient and the Fourier
-//    basis) to the inlet coefficients; the pressure equilibrium sends it to all
-//    of the site's own populations through u(A_t[:, s]); the outlet flux term of
-//    the objective enters here too.
+//    upstream site or the site's own opposite population for a wall link).  Every
+//    population location is read by at most one link, so the push needs no
+//    atomics; the populations that leave through iolets are read by nobody and
+//    are set to zero here.
+//  * at a site with iolet links the same thread turns the adjoints of the values
+//    those links pulled (the incoming iolet populations) into their sources: the
+//    Ladd term sends its adjoint to the site's opposite population and (times its
+//    coefficient and the tabulated Fourier basis) to the inlet coefficients; the
+//    pressure equilibrium sends it to all of the site's own populations through
+//    u(A_t[:, s]); the outlet flux term of the objective enters here too.  What
+//    goes to the site's own populations of A_t is held in a per-site pending
+//    buffer and added when the site reads them in the next (earlier) reverse
+//    step, after every push of this step has landed; k_adj_flush adds what is
+//    left at the end of a segment.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "adjoint.hpp"
 #include "kernels.hpp"
@@ -33,7 +39,7 @@
 
 namespace hlb {
 
-constexpr int kObjBlock = 1024;
+constexpr int kObjParts = 256;  // most blocks of the objective's partial sums
 
 // pre-collision populations (deviations) of site s from a state with filled
 // ghosts, given its decoded links j
@@ -98,45 +104,138 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// forward objective terms of one step: Q(t) and sum over D of WSS(f_t)
+// forward objective terms of one step: Q(t) and sum over D of WSS(f_t).  Each
+// block sums a fixed share of the outlet links and dome sites (a grid-stride
+// loop, then a fixed reduction tree) into part[2 b], part[2 b + 1]; a second
+// kernel adds the partials in block order, so the result is deterministic.
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool SC>
-__global__ __launch_bounds__(kObjBlock) void k_objective(
+__global__ __launch_bounds__(kBlock) void k_objective(
     const typename Store<ST>::T* __restrict__ A, Table tb, int32_t n,
     Ghosts G, const int32_t* __restrict__ out_links, int32_t n_out,
     const int32_t* __restrict__ dome, int32_t n_dome, const float* __restrict__ normal,
-    float omega, double* __restrict__ q_out, double* __restrict__ w_out) {
+    float omega, double* __restrict__ part) {
     using C = Codec<Q, ST, SC>;
-    __shared__ double red[kObjBlock / 64];
+    __shared__ double red[kBlock / 64];
     double q = 0.0, w = 0.0;
-    for (int32_t k = threadIdx.x; k < n_out; k += kObjBlock) {
-        const int32_t l = out_links[k];
-        const int32_t s = G.site[l];
-        const int i = G.dir[l];
-        const int o = opp(i);
-        q += (double)C::dec(o, A[tix<Q>(o, s)]) -
-             (double)C::dec(i, A[tix<Q>(i, ghost_slot(G, n, l))]);
-    }
-    for (int32_t k = threadIdx.x; k < n_dome; k += kObjBlock) {
-        const int32_t s = dome[k];
-        float d[Q];
-        int32_t j[Q];
-        links_site<Q>(tb, s, j);
-        gather_pre<Q, ST, SC>(A, s, n, d, j);
-        float drho, mx, my, mz;
-        moments<Q>(d, drho, mx, my, mz);
-        const float ir = 1.0f / (1.0f + drho);
-        float tx, ty, tz;
-        shear<Q>(d, drho, mx * ir, my * ir, mz * ir, omega, normal[s], normal[n + s],
-                 normal[2 * (int64_t)n + s], tx, ty, tz);
-        w += sqrtf(tx * tx + ty * ty + tz * tz);
+    const int64_t items = (int64_t)n_out + n_dome;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < items;
+         k += (int64_t)gridDim.x * kBlock) {
+        if (k < n_out) {
+            const int32_t l = out_links[k];
+            const int32_t s = G.site[l];
+            const int i = G.dir[l];
+            const int o = opp(i);
+            q += (double)C::dec(o, A[tix<Q>(o, s)]) -
+                 (double)C::dec(i, A[tix<Q>(i, ghost_slot(G, n, l))]);
+        } else {
+            const int32_t s = dome[k - n_out];
+            float d[Q];
+            int32_t j[Q];
+            links_site<Q>(tb, s, j);
+            gather_pre<Q, ST, SC>(A, s, n, d, j);
+            float drho, mx, my, mz;
+            moments<Q>(d, drho, mx, my, mz);
+            const float ir = 1.0f / (1.0f + drho);
+            float tx, ty, tz;
+            shear<Q>(d, drho, mx * ir, my * ir, mz * ir, omega, normal[s], normal[n + s],
+                     normal[2 * (int64_t)n + s], tx, ty, tz);
+            w += sqrtf(tx * tx + ty * ty + tz * tz);
+        }
     }
     const double qs = block_sum(q, red);
     const double ws = block_sum(w, red);
     if (threadIdx.x == 0) {
-        *q_out = qs;
-        *w_out = ws;
+        part[2 * blockIdx.x] = qs;
+        part[2 * blockIdx.x + 1] = ws;
     }
+}
+
+// one wavefront: lane k adds partials k, k + 64, ... in order, then a fixed
+// butterfly over the lanes
+__global__ __launch_bounds__(64) void k_objective_final(const double* __restrict__ part,
+                                                        int32_t nparts, double* __restrict__ q_out,
+                                                        double* __restrict__ w_out) {
+    double q = 0.0, w = 0.0;
+    for (int32_t b = (int32_t)threadIdx.x; b < nparts; b += 64) {
+        q += part[2 * b];
+        w += part[2 * b + 1];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        q += __shfl_xor(q, off, 64);
+        w += __shfl_xor(w, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        *q_out = q;
+        *w_out = w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse step at iolet sites (called by the site's own thread)
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool SC>
+__device__ inline void iolet_adjoint(const typename Store<ST>::T* __restrict__ A, int32_t s,
+                                           const int32_t (&j)[Q], const float (&fh)[Q],
+                                           const Ghosts& G, const IoletAdj& I, int64_t kis,
+                                           int32_t n) {
+    using C = Codec<Q, ST, SC>;
+    using Lt = Lat<Q>;
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(i, A[tix<Q>(i, s)]);
+    float drho, mx, my, mz;
+    moments<Q>(d, drho, mx, my, mz);
+    const float rA = 1.0f + drho;
+    const float ir = 1.0f / rA;
+    const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+    const double qbar = I.q_index >= 0 ? 2.0 * (I.q_tape[I.q_index] - I.q_target) : 0.0;
+    float acc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[i] = 0.f;
+    // the site's iolet links are consecutive in the link list, in direction order
+    int64_t l = I.S.lo[kis];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (j[i] < n) continue;
+        const int o = opp(i);
+        const int kio = G.iolet[l];
+        const DevIolet io = G.iolets[kio];
+        const int64_t step = ((int64_t)I.t - G.vals_t0) * G.n_iolets + kio;
+        float gh = fh[i];  // adjoint of the incoming value the link pulled
+        if (kio == I.outlet && I.q_index >= 0) {
+            gh -= (float)qbar;
+            acc[o] += (float)qbar;
+        }
+        if (io.kind == 1) {
+            acc[o] += gh;
+            // d value / d(mean, cos_h, sin_h), with the basis tabulated for this step
+            const double c = (double)gh * (double)G.coef[l];
+            double* th = I.theta_acc + l * I.nbasis;
+            const double* bs = G.basis + step * G.basis_stride;
+            th[0] += c;
+            for (int h = 1; h <= io.n_harm; ++h) {
+                th[h] += c * bs[2 * (h - 1)];
+                th[io.n_harm + h] += c * bs[2 * (h - 1) + 1];
+            }
+        } else {
+            const float rk = (float)G.vals[step];
+            const float cix = Lt::cx[i], ciy = Lt::cy[i], ciz = Lt::cz[i];
+            const float cu = cix * ux + ciy * uy + ciz * uz;
+            const float sc = Lt::w[i] * rk;
+            const float gx = sc * (3.0f * cix + 9.0f * cu * cix - 3.0f * ux);
+            const float gy = sc * (3.0f * ciy + 9.0f * cu * ciy - 3.0f * uy);
+            const float gz = sc * (3.0f * ciz + 9.0f * cu * ciz - 3.0f * uz);
+            const float gi = gh * ir;
+#pragma unroll
+            for (int jd = 0; jd < Q; ++jd)
+                acc[jd] += gi * ((Lt::cx[jd] - ux) * gx + (Lt::cy[jd] - uy) * gy + (Lt::cz[jd] - uz) * gz);
+        }
+        ++l;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) I.pend[kis * Q + i] = acc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -147,8 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
     float* __restrict__ gout, Table tb, int32_t n, float omega,
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
-    const float* __restrict__ wss_w, const float* __restrict__ normal) {
+    const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
     using Lt = Lat<Q>;
+    using C = Codec<Q, ST, SC>;
     static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
     __shared__ StageLds lds;
     const int32_t grp = blockIdx.x;
@@ -162,6 +262,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     float g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = gin[tix<Q>(i, s)];
+    // a site with iolet links: find its entry and add what the later step left pending
+    int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
+#pragma unroll
+    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+    int64_t kis = -1;
+    if (top >= n) {
+        int64_t l = -1;
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (l < 0 && j[i] >= n) l = ghost_link<Q>(G, n, j[i], i);
+        kis = I.link_is[l];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] += I.pend[kis * Q + i];
+    }
 
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -232,73 +346,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
         // an iolet link: the population opp(i) of this site leaves the domain
         if (j[i] >= n) gout[tix<Q>(opp(i), s)] = 0.0f;
     }
+    if (kis >= 0) iolet_adjoint<Q, ST, SC>(A, s, j, fh, G, I, kis, n);
 }
 
-// ---------------------------------------------------------------------------
-// reverse step at iolet sites
-// ---------------------------------------------------------------------------
-template <int Q, int ST, bool SC>
-__global__ __launch_bounds__(kBlock) void k_adj_iolet(
-    const typename Store<ST>::T* __restrict__ A, float* __restrict__ gout, Ghosts G,
-    IoletSites S, int32_t n, double t, int32_t outlet, const double* __restrict__ q_tape,
-    int64_t q_index, double q_target, double* __restrict__ theta_acc, int32_t nbasis) {
-    using C = Codec<Q, ST, SC>;
-    using Lt = Lat<Q>;
-    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= S.count) return;
-    const int32_t s = S.site[k];
-    float d[Q];
+// adds what the last reverse step left pending to the sites' own populations
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_adj_flush(float* __restrict__ gout, IoletAdj I) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= I.S.count) return;
+    const int32_t s = I.S.site[k];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(i, A[tix<Q>(i, s)]);
-    float drho, mx, my, mz;
-    moments<Q>(d, drho, mx, my, mz);
-    const float rA = 1.0f + drho;
-    const float ir = 1.0f / rA;
-    const float ux = mx * ir, uy = my * ir, uz = mz * ir;
-    const double qbar = q_index >= 0 ? 2.0 * (q_tape[q_index] - q_target) : 0.0;
-    float acc[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) acc[i] = 0.f;
-    for (int32_t l = S.lo[k]; l < S.hi[k]; ++l) {
-        const int i = G.dir[l];
-        const int o = opp(i);
-        const int kio = G.iolet[l];
-        const DevIolet io = G.iolets[kio];
-        float gh = gout[tix<Q>(i, ghost_slot(G, n, l))];
-        if (kio == outlet && q_index >= 0) {
-            gh -= (float)qbar;
-            acc[o] += (float)qbar;
-        }
-        if (io.kind == 1) {
-            acc[o] += gh;
-            // d value / d(mean, cos_h, sin_h)
-            const double c = (double)gh * (double)G.coef[l];
-            double* th = theta_acc + (int64_t)l * nbasis;
-            th[0] += c;
-            for (int h = 1; h <= io.n_harm; ++h) {
-                const double ph = fmod((double)h * t, io.period) / io.period;
-                double sv, cv;
-                sincospi(2.0 * ph, &sv, &cv);
-                th[h] += c * cv;
-                th[io.n_harm + h] += c * sv;
-            }
-        } else {
-            const float rk = (float)iolet_value(io, G.harm, t);
-            const float cix = Lt::cx[i], ciy = Lt::cy[i], ciz = Lt::cz[i];
-            const float cu = cix * ux + ciy * uy + ciz * uz;
-            const float sc = Lt::w[i] * rk;
-            const float gx = sc * (3.0f * cix + 9.0f * cu * cix - 3.0f * ux);
-            const float gy = sc * (3.0f * ciy + 9.0f * cu * ciy - 3.0f * uy);
-            const float gz = sc * (3.0f * ciz + 9.0f * cu * ciz - 3.0f * uz);
-            const float gi = gh * ir;
-#pragma unroll
-            for (int jd = 0; jd < Q; ++jd)
-                acc[jd] += gi * ((Lt::cx[jd] - ux) * gx + (Lt::cy[jd] - uy) * gy + (Lt::cz[jd] - uz) * gz);
-        }
+    for (int i = 0; i < Q; ++i) {
+        gout[tix<Q>(i, s)] += I.pend[k * Q + i];
+        I.pend[k * Q + i] = 0.f;
     }
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-        if (acc[i] != 0.f) gout[tix<Q>(i, s)] += acc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -306,47 +367,54 @@ __global__ __launch_bounds__(kBlock) void k_adj_iolet(
 // ---------------------------------------------------------------------------
 static inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, const Objective& O,
-                            const float* normal, float omega, double* q_out, double* w_out,
-                            hipStream_t s) {
-    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
-        using Tg = decltype(tag);
-        using T = typename Store<Tg::ST>::T;
-        k_objective<Tg::Q, Tg::ST, Tg::SC><<<1, kObjBlock, 0, s>>>(
-            static_cast<const T*>(A), L.tb, (int32_t)L.n, G, O.out_links, O.n_out, O.dome,
-            O.n_dome, normal, omega, q_out, w_out);
-        return hipGetLastError();
-    });
+int32_t objective_parts(int64_t items) {
+    return (int32_t)std::min<int64_t>(kObjParts, std::max<int64_t>(1, (items + kBlock - 1) / kBlock));
 }
 
-hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletSites& S, const void* A,
-                           const float* gin, float* gout, float omega, const float* alpha,
-                           double* alpha_hat, const float* wss_w, const float* normal, int64_t t,
-                           int32_t outlet, const double* q_tape, int64_t q_index,
-                           double q_target, double* theta_acc, int32_t nbasis, hipStream_t s) {
-    if (L.n == 0) return hipSuccess;
+hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, const Objective& O,
+                            const float* normal, float omega, double* part, double* q_out,
+                            double* w_out, hipStream_t s) {
+    const int32_t parts = objective_parts((int64_t)O.n_out + O.n_dome);
     hipError_t e = dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        k_objective<Tg::Q, Tg::ST, Tg::SC><<<(unsigned)parts, kBlock, 0, s>>>(
+            static_cast<const T*>(A), L.tb, (int32_t)L.n, G, O.out_links, O.n_out, O.dome,
+            O.n_dome, normal, omega, part);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    k_objective_final<<<1, 64, 0, s>>>(part, parts, q_out, w_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, const void* A,
+                           const float* gin, float* gout, float omega, const float* alpha,
+                           double* alpha_hat, const float* wss_w, const float* normal,
+                           hipStream_t s) {
+    if (L.n == 0) return hipSuccess;
+    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
         if (alpha)
             k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, true><<<blocks(L.n), kBlock, 0, s>>>(
                 static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, alpha, alpha_hat,
-                wss_w, normal);
+                wss_w, normal, G, I);
         else
             k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, false><<<blocks(L.n), kBlock, 0, s>>>(
                 static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
-                alpha_hat, wss_w, normal);
+                alpha_hat, wss_w, normal, G, I);
         return hipGetLastError();
     });
-    if (e != hipSuccess || S.count == 0) return e;
-    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
-        using Tg = decltype(tag);
-        using T = typename Store<Tg::ST>::T;
-        k_adj_iolet<Tg::Q, Tg::ST, Tg::SC><<<blocks(S.count), kBlock, 0, s>>>(
-            static_cast<const T*>(A), gout, G, S, (int32_t)L.n, (double)t, outlet, q_tape, q_index,
-            q_target, theta_acc, nbasis);
-        return hipGetLastError();
-    });
+}
+
+hipError_t launch_adj_flush(int q, float* gout, const IoletAdj& I, hipStream_t s) {
+    if (I.S.count == 0) return hipSuccess;
+    if (q == 15)
+        k_adj_flush<15><<<blocks(I.S.count), kBlock, 0, s>>>(gout, I);
+    else
+        k_adj_flush<19><<<blocks(I.S.count), kBlock, 0, s>>>(gout, I);
+    return hipGetLastError();
 }
 
 }  // namespace hlb

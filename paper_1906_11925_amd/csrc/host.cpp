@@ -147,6 +147,7 @@ struct hemelb_lb {
     int32_t nfluid = 0, nblocks = 0;
     int addressing = HEMELB_ADDR_TABLE32;
     int32_t* g_slot = nullptr;  // ghost slot of each iolet link (block addressing)
+    int32_t* g_cell_link = nullptr;  // [cells][q]: iolet link pulling (cell, i), or -1
     uint32_t* gblob = nullptr;  // staged block records per 4-tile group
     int32_t* grp = nullptr;
     int64_t blob_words = 0;
@@ -160,6 +161,9 @@ struct hemelb_lb {
     double* d_vals = nullptr;  // iolet values for a batch of steps
     int64_t vals_cap = 0;      // steps the buffer holds
     int64_t vals_t0 = 0;
+    double* d_basis = nullptr;  // Fourier basis of velocity iolets per step (adjoint)
+    int64_t basis_cap = 0;      // steps the buffer holds
+    int32_t basis_stride = 0;   // doubles per (step, iolet): 2 x the most harmonics
     int32_t* perm = nullptr;  // Morton index -> caller index (null: identity)
     float* normal = nullptr;  // [3][n] Morton order
     float* alpha = nullptr;
@@ -203,6 +207,7 @@ struct hemelb_lb {
     float* d_wss_w = nullptr;
     double* d_qtape = nullptr;
     double* d_wtape = nullptr;
+    double* d_opart = nullptr;  // partial sums of the objective's blocks
 
     // adjoint
     std::vector<void*> tape;  // K+1 population buffers of a recompute segment
@@ -211,6 +216,8 @@ struct hemelb_lb {
     double* alpha_hat = nullptr;
     double* theta_acc = nullptr;
     int32_t nbasis = 1;
+    float* is_pend = nullptr;  // adjoint pending for iolet sites' own populations [n_is][q]
+    int32_t* is_link = nullptr;  // entry of each iolet link's site among the iolet sites
     int32_t* is_site = nullptr;
     int32_t* is_lo = nullptr;
     int32_t* is_hi = nullptr;
@@ -225,8 +232,9 @@ struct hemelb_lb {
                            bfl};
     }
     hlb::Ghosts ghosts() const {
-        return hlb::Ghosts{nghost,   g_slot, g_site, g_dir,   g_iolet,  g_coef,
-                           d_iolets, d_harm, d_vals, vals_t0, n_iolets};
+        return hlb::Ghosts{nghost,  g_slot,  g_cell_link, g_site,   g_dir,   g_iolet,
+                           g_coef,  d_iolets, d_harm,     d_vals,   vals_t0, n_iolets,
+                           d_basis, basis_stride};
     }
     size_t elem() const { return storage == HEMELB_STORE_F32 ? 4 : 2; }
     // algorithmic HBM bytes of one site update: populations read and written once,
@@ -267,11 +275,14 @@ void release(hemelb_lb* h) {
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
                     h->t16,       h->toff,      h->tlist,      h->brec,      h->gmask,
                     h->bnbr,      h->tblock,    h->g_slot,     h->gblob,     h->grp,
+                    h->g_cell_link, h->is_link,
                     h->g_iolet,   h->g_coef,    h->d_iolets,   h->d_harm,    h->perm,
                     h->normal,    h->alpha,     h->partial,    h->tot,       h->flag,
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
+                    h->d_opart,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
-                    h->is_lo,     h->is_hi,     h->d_vals};
+                    h->is_pend,
+                    h->is_lo,     h->is_hi,     h->d_vals,     h->d_basis};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (void* p : h->tape)
@@ -373,6 +384,7 @@ struct BlockPlan {
     std::vector<int32_t> nbr;        // [nfluid][27]
     std::vector<int32_t> tblock;     // block of the first site of each tile
     std::vector<int32_t> gslot;      // ghost slot of each iolet link
+    std::vector<int32_t> cell_link;  // [cells][q]: iolet link pulling (cell, i), or -1
     std::vector<uint32_t> blob;      // staged records of every 4-tile group (16-byte units)
     std::vector<int32_t> grp;        // per group: blob offset, nown | nrec << 16
     double fallback_bytes = 0;       // global records read by groups whose blob would not fit
@@ -478,6 +490,9 @@ bool build_blocks(const hemelb_lb_desc_t* d, const HostLat& lat, const std::vect
         P.gslot[c.link] = (int32_t)(n + g);
     }
     P.ncells = g + 1;
+    P.cell_link.assign((size_t)std::max<int64_t>(1, P.ncells) * q, -1);
+    for (int64_t l = 0; l < ng; ++l)
+        P.cell_link[(size_t)(P.gslot[l] - n) * q + gdir[l]] = (int32_t)l;
 
     // the 27 blocks around every fluid block
     P.nbr.assign((size_t)P.nfluid * 27, -1);
@@ -646,9 +661,23 @@ bool build_blocks(const hemelb_lb_desc_t* d, const HostLat& lat, const std::vect
     return true;
 }
 
-// iolet values for times t0 .. t0 + count - 1 into the handle's table
-int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
+// iolet values (and with `basis` the velocity iolets' Fourier basis) for times
+// t0 .. t0 + count - 1 into the handle's tables
+int fill_series(hemelb_lb* h, int64_t t0, int64_t count, bool basis = false) {
     if (h->n_iolets == 0) return HEMELB_OK;
+    basis = basis && h->basis_stride > 0;
+    if (basis && count > h->basis_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+        if (h->d_basis) {
+            (void)hipFree(h->d_basis);
+            h->device_bytes -= h->basis_cap * h->n_iolets * h->basis_stride * (int64_t)sizeof(double);
+            h->d_basis = nullptr;
+        }
+        int rc = dev_alloc(h, &h->d_basis, (size_t)(count * h->n_iolets * h->basis_stride),
+                           "iolet basis");
+        if (rc) return rc;
+        h->basis_cap = count;
+    }
     if (count > h->vals_cap) {
         HIP_TRY(hipStreamSynchronize(h->stream), "sync");
         if (h->d_vals) {
@@ -662,7 +691,7 @@ int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
         h->vals_cap = cap;
     }
     HIP_TRY(hlb::launch_iolet_series(h->d_iolets, h->d_harm, h->n_iolets, t0, count, h->d_vals,
-                                     h->stream),
+                                     basis ? h->d_basis : nullptr, h->basis_stride, h->stream),
             "iolet series");
     h->vals_t0 = t0;
     return HEMELB_OK;
@@ -676,7 +705,7 @@ int do_step(hemelb_lb* h) {
         HIP_TRY(hlb::launch_ghost_fill(L, h->ghosts(), src, h->t, h->stream), "ghost fill");
     if (h->obj_set && h->t >= h->w0 && h->t < h->w1) {
         const hlb::Objective O{h->d_out_links, h->n_out, h->d_dome, (int32_t)h->n_dome};
-        HIP_TRY(hlb::launch_objective(L, h->ghosts(), src, O, h->normal, h->omega,
+        HIP_TRY(hlb::launch_objective(L, h->ghosts(), src, O, h->normal, h->omega, h->d_opart,
                                       h->d_qtape + (h->t - h->w0), h->d_wtape + (h->t - h->w0),
                                       h->stream),
                 "objective");
@@ -938,7 +967,7 @@ int64_t planned_device_bytes(const HostPlan& P, int q, size_t elem) {
     int64_t b = 2 * (int64_t)q * P.slots * (int64_t)elem;
     b += (int64_t)(P.bp.rec.size() * sizeof(hlb::BlockRec) + P.bp.gmask.size() * 8 +
                    P.bp.nbr.size() * 4 + P.bp.tblock.size() * 4 + P.bp.gslot.size() * 4 +
-                   P.bp.blob.size() * 4 + P.bp.grp.size() * 4);
+                   P.bp.blob.size() * 4 + P.bp.grp.size() * 4 + P.bp.cell_link.size() * 4);
     b += (int64_t)(P.tbl.size() * 4 + P.t16.size() * 2 + P.toff.size() * 4 + P.tlist.size() * 4);
     b += (int64_t)(P.gsite.size() * 4 + P.gdir.size() + P.giol.size() + P.gcoef.size() * 4);
     b += (int64_t)(P.dio.size() * sizeof(hlb::DevIolet) + P.harm.size() * 8);
@@ -1147,6 +1176,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         TRY(dev_upload(h, &h->bnbr, P.bp.nbr, "neighbour blocks"));
         TRY(dev_upload(h, &h->tblock, P.bp.tblock, "tile blocks"));
         TRY(dev_upload(h, &h->g_slot, P.bp.gslot, "ghost slots"));
+        TRY(dev_upload(h, &h->g_cell_link, P.bp.cell_link, "ghost cell links"));
         TRY(dev_upload(h, &h->gblob, P.bp.blob, "staged block records"));
         TRY(dev_upload(h, &h->grp, P.bp.grp, "staged block groups"));
         h->blob_words = (int64_t)P.bp.blob.size();
@@ -1413,7 +1443,7 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     for (void** p : {(void**)&h->d_out_links, (void**)&h->d_dome, (void**)&h->d_wss_w,
-                     (void**)&h->d_qtape, (void**)&h->d_wtape})
+                     (void**)&h->d_qtape, (void**)&h->d_wtape, (void**)&h->d_opart})
         if (*p) {
             (void)hipFree(*p);
             *p = nullptr;
@@ -1446,6 +1476,9 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
     if ((rc = dev_upload(h, &h->d_dome, dome, "objective dome"))) return rc;
     if ((rc = dev_upload(h, &h->d_wss_w, w, "objective weights"))) return rc;
     std::vector<double> zeros(nw, 0.0);
+    const std::vector<double> parts(
+        2 * (size_t)hlb::objective_parts((int64_t)outl.size() + (int64_t)dome.size()), 0.0);
+    if ((rc = dev_upload(h, &h->d_opart, parts, "objective partials"))) return rc;
     if ((rc = dev_upload(h, &h->d_qtape, zeros, "flux tape"))) return rc;
     if ((rc = dev_upload(h, &h->d_wtape, zeros, "shear tape"))) return rc;
     h->n_out = (int32_t)outl.size();
@@ -1517,6 +1550,7 @@ int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
     for (auto& io : h->h_iolets)
         if (io.kind == HEMELB_IOLET_VELOCITY) hmax = std::max(hmax, io.n_harm);
     h->nbasis = 1 + 2 * hmax;
+    h->basis_stride = 2 * hmax;
     if (!h->theta_acc && h->nghost > 0 &&
         (rc = dev_alloc(h, &h->theta_acc, (size_t)h->nghost * h->nbasis, "theta adjoint")))
         return rc;
@@ -1530,11 +1564,17 @@ int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
             hi.push_back((int32_t)e);
             l = e;
         }
+        std::vector<int32_t> of_link((size_t)h->nghost);
+        for (size_t k = 0; k < st.size(); ++k)
+            for (int32_t l = lo[k]; l < hi[k]; ++l) of_link[l] = (int32_t)k;
+        if ((rc = dev_upload(h, &h->is_link, of_link, "iolet link sites"))) return rc;
         if ((rc = dev_upload(h, &h->is_site, st, "iolet sites"))) return rc;
         if ((rc = dev_upload(h, &h->is_lo, lo, "iolet sites"))) return rc;
         if ((rc = dev_upload(h, &h->is_hi, hi, "iolet sites"))) return rc;
         h->n_is = (int64_t)st.size();
+        if ((rc = dev_alloc(h, &h->is_pend, (size_t)h->n_is * h->q, "iolet pending"))) return rc;
     }
+    if (h->is_pend) HIP_TRY(hlb::launch_zero_words(h->is_pend, h->n_is * h->q, h->stream), "zero");
     h->gcur = 0;
     hlb::Layout Lg = h->layout();
     Lg.storage = HEMELB_STORE_F32;
@@ -1557,7 +1597,7 @@ int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0,
                     (long long)h->adj_t);
     if (!checkpoint && h->n > 0) return fail(HEMELB_EINVAL, "checkpoint is NULL");
     HIP_TRY(hipSetDevice(h->device), "set device");
-    int rc = fill_series(h, t0, steps + 1);
+    int rc = fill_series(h, t0, steps + 1, true);
     if (rc) return rc;
     h->ghosts_ready = false;  // the forward's values table is overwritten
     const hlb::Layout L = h->layout();
@@ -1572,17 +1612,20 @@ int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0,
                 "recompute");
     }
     const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
+    hlb::IoletAdj I{S,          h->is_link,  h->is_pend,     0.0,      h->obj_outlet,
+                    h->d_qtape, -1,          h->q_target,    h->theta_acc, h->nbasis};
     for (int64_t m = steps - 1; m >= 0; --m) {
         const int64_t t = t0 + m;
         const bool inw = t >= h->w0 && t < h->w1;
-        HIP_TRY(hlb::launch_adj_step(L, G, S, h->tape[m], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
+        I.t = (double)t;
+        I.q_index = inw ? t - h->w0 : -1;
+        HIP_TRY(hlb::launch_adj_step(L, G, I, h->tape[m], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
                                      h->omega, h->alpha, h->alpha_hat, inw ? h->d_wss_w : nullptr,
-                                     h->normal, t, h->obj_outlet, h->d_qtape,
-                                     inw ? t - h->w0 : -1, h->q_target, h->theta_acc, h->nbasis,
-                                     h->stream),
+                                     h->normal, h->stream),
                 "adjoint step");
         h->gcur ^= 1;
     }
+    HIP_TRY(hlb::launch_adj_flush(h->q, h->ghat[h->gcur], I, h->stream), "adjoint flush");
     h->adj_t = t0;
     return HEMELB_OK;
 }

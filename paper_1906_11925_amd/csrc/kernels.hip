@@ -100,6 +100,25 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
         d[i] = C::dec(i, src[tix<Q>(dir, site)]);
     }
     if constexpr (BFL) apply_bfl<Q, ST, SC>(src, s, n, j, d);
+#if HLB_FUSE_GHOSTS
+    // directions of the site's iolet links and the first of those links (they are
+    // consecutive in the link list, in direction order), for the epilogue
+    uint32_t gmask = 0;
+    int64_t gl = -1;
+    {
+        int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
+#pragma unroll
+        for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+        if (top >= n) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i)
+                if (j[i] >= n) {
+                    if (gl < 0) gl = ghost_link<Q>(G, n, j[i], i);
+                    gmask |= 1u << i;
+                }
+        }
+    }
+#endif
 
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -126,35 +145,12 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
     // order.  With one slot per link (table encodings) the first one is the
     // smallest ghost slot the site pulls from; with shared ghost cells (block
     // addressing) it is found by a binary search of the list.
-    int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
-#pragma unroll
-    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
-    if (top >= n) {
-        uint32_t mask = 0;
-        int32_t first = 0x7fffffff;
+    if (gmask) {
 #pragma unroll
         for (int i = 1; i < Q; ++i)
-            if (j[i] >= n) {
-                mask |= 1u << i;
-                first = min(first, j[i]);
-            }
-        int64_t l = first - n;
-        if (G.slot) {
-            int64_t lo = 0, hi = G.count;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (G.site[mid] < s)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            l = lo;
-        }
-#pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if (mask & (1u << i)) {
-                dst[tix<Q>(i, ghost_slot(G, n, l))] = C::enc(i, ghost_value<Q>(G, l, i, vs, t_next));
-                ++l;
+            if (gmask & (1u << i)) {
+                dst[tix<Q>(i, ghost_slot(G, n, gl))] = C::enc(i, ghost_value<Q>(G, gl, i, vs, t_next));
+                ++gl;
             }
     }
 #else
@@ -199,12 +195,26 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
 __global__ __launch_bounds__(kBlock) void k_iolet_series(const DevIolet* __restrict__ iolets,
                                                           const double* __restrict__ harm,
                                                           int32_t n_iolets, int64_t t0,
-                                                          int64_t count, double* __restrict__ vals) {
+                                                          int64_t count, double* __restrict__ vals,
+                                                          double* __restrict__ basis,
+                                                          int32_t basis_stride) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= count * n_iolets) return;
     const int64_t m = e / n_iolets;
     const int k = (int)(e % n_iolets);
-    vals[e] = iolet_value(iolets[k], harm, (double)(t0 + m));
+    const DevIolet io = iolets[k];
+    const double t = (double)(t0 + m);
+    vals[e] = iolet_value(io, harm, t);
+    if (basis && io.kind == 1) {
+        double* b = basis + e * basis_stride;
+        for (int h = 1; h <= io.n_harm; ++h) {
+            const double ph = fmod((double)h * t, io.period) / io.period;  // in [0, 1)
+            double sv, cv;
+            sincospi(2.0 * ph, &sv, &cv);
+            b[2 * (h - 1)] = cv;
+            b[2 * (h - 1) + 1] = sv;
+        }
+    }
 }
 
 template <int Q, int ST, bool SC>
@@ -505,10 +515,11 @@ hipError_t launch_zero(const Layout& L, void* A, hipStream_t s) {
 bool ghosts_fused() { return HLB_FUSE_GHOSTS != 0; }
 
 hipError_t launch_iolet_series(const DevIolet* iolets, const double* harm, int32_t n_iolets,
-                               int64_t t0, int64_t count, double* vals, hipStream_t s) {
+                               int64_t t0, int64_t count, double* vals, double* basis,
+                               int32_t basis_stride, hipStream_t s) {
     if (n_iolets == 0 || count <= 0) return hipSuccess;
     k_iolet_series<<<blocks_for(count * n_iolets), kBlock, 0, s>>>(iolets, harm, n_iolets, t0,
-                                                                   count, vals);
+                                                                   count, vals, basis, basis_stride);
     return hipGetLastError();
 }
 

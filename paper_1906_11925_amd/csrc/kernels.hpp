@@ -101,6 +101,7 @@ struct Layout {
 struct Ghosts {
     int64_t count;
     const int32_t* slot;
+    const int32_t* cell_link;  // with shared ghost cells: [cells][q] link pulling (cell, i), or -1
     const int32_t* site;   // Morton site index of each iolet link
     const uint8_t* dir;    // direction of the link
     const uint8_t* iolet;  // iolet id
@@ -110,11 +111,18 @@ struct Ghosts {
     const double* vals;    // iolet values per step: vals[(t - vals_t0) * n_iolets + k]
     int64_t vals_t0;
     int32_t n_iolets;
+    // Fourier basis of velocity iolets per step (adjoint only, else null):
+    // basis[((t - vals_t0) * n_iolets + k) * basis_stride + 2 (h - 1) + {0, 1}] =
+    // cos, sin of 2 pi h t / period_k for h = 1 .. n_harm_k
+    const double* basis;
+    int32_t basis_stride;
 };
 
-// vals[m * n_iolets + k] = value of iolet k at time t0 + m, for m < count
+// vals[m * n_iolets + k] = value of iolet k at time t0 + m, for m < count; with
+// basis != null also the Fourier basis of velocity iolets (layout as Ghosts::basis)
 hipError_t launch_iolet_series(const DevIolet* iolets, const double* harm, int32_t n_iolets,
-                               int64_t t0, int64_t count, double* vals, hipStream_t s);
+                               int64_t t0, int64_t count, double* vals, double* basis,
+                               int32_t basis_stride, hipStream_t s);
 
 hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t t,
                              hipStream_t s);

@@ -362,6 +362,12 @@ __device__ inline int32_t ghost_slot(const Ghosts& G, int32_t n, int64_t l) {
     return G.slot ? G.slot[l] : n + (int32_t)l;
 }
 
+// iolet link that pulls direction i from ghost slot `slot`
+template <int Q>
+__device__ inline int64_t ghost_link(const Ghosts& G, int32_t n, int32_t slot, int i) {
+    return G.slot ? (int64_t)G.cell_link[(int64_t)(slot - n) * Q + i] : (int64_t)(slot - n);
+}
+
 // moments of FP32 deviations: drho = sum d, m = sum c d (constant-folded per lattice)
 template <int Q>
 __device__ inline void moments(const float (&d)[Q], float& drho, float& mx, float& my, float& mz) {
