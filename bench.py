@@ -200,6 +200,37 @@ def adjoint_run(steps=4000, K=200, window=1000):
             "dJ_dalpha_norm": float(np.linalg.norm(da))}
 
 
+def render_run(lb, geom, size=1024, frames=20):
+    """In-situ volume rendering of the flow speed |u| of the benchmark's state:
+    a size x size orthographic view of the whole vessel (step half a lattice
+    spacing), timed with HIP events over `frames` frames."""
+    import numpy as np
+    import torch
+    from workloads.camera import orbit_view, ramp_lut
+    _, u, _ = lb.observables()
+    speed = torch.linalg.vector_norm(u, dim=1).contiguous()
+    hi = float(speed.max())
+    c = geom.coords
+    centre = (c.min(axis=0) + c.max(axis=0)) / 2.0
+    extent = float(np.linalg.norm(c.max(axis=0) - c.min(axis=0)))
+    view = orbit_view(centre, extent, 35, 25, size, size, pixel=extent / size, step=0.5)
+    lut = ramp_lut(0.05)
+    image = lb.render(speed, view, lut, scale=1.0 / max(hi, 1e-30))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(frames):
+        lb.render(speed, view, lut, scale=1.0 / max(hi, 1e-30), image=image)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / frames
+    lit = float((image[..., 3] > 0).float().mean())
+    log(f"[bench] render {size}x{size}: {ms:.3f} ms/frame")
+    return {"field": "speed", "width": size, "height": size, "steps": view["steps"],
+            "step_lattice_units": 0.5, "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
+            "rays_per_s": size * size / (ms * 1e-3), "lit_fraction": lit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +300,7 @@ def main():
     achieved = bpu * n / (avg_ms * 1e-3) / 1e9
     log(f"[bench] {glups:.2f} GLUPS, {ms_step:.4f} ms/step, kernel {avg_ms:.4f} ms "
         f"-> {achieved:.0f} GB/s algorithmic")
+    render = None if args.no_extra else render_run(lb, geom)
     lb.close()
 
     pop_bytes = 2 * args.lattice * (4 if args.storage == "f32" else 2)
@@ -290,6 +322,8 @@ def main():
         copy_probe(b, a, nbytes)
     torch.cuda.synchronize()
     copy_gbs = 2 * nbytes * reps / (time.perf_counter() - t0) / 1e9
+    if render:
+        extra["render"] = render
     extra["copy_GBs"] = copy_gbs
     extra["frac_of_copy"] = achieved / copy_gbs
     del a, b

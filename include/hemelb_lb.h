@@ -291,6 +291,46 @@ int hemelb_lb_kernel_timing(hemelb_lb_t h, int64_t max_launches);
 int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches);
 
 /*
+ * In-situ direct volume rendering of a lattice property by ray marching (the
+ * visualization of Section 3.C.2: voxels sampled from a volume, viewing
+ * parameters and a transfer-function look-up table with steerable scale and
+ * offset).  The volume holds one value per fluid site at the site's integer
+ * coordinates (voxel centres); all other points are empty.
+ *
+ * A view gives fixed-point integer vectors, HEMELB_VIEW_FIX units per lattice
+ * spacing: ray (i, j), 0 <= i < width, 0 <= j < height, starts at
+ * P0 = origin + i * right + j * up and samples P_k = P0 + k * dir, k = 0 .. steps-1.
+ * A sample takes the nearest voxel, x = floor((P_k + FIX/2) / FIX) per axis.  At a
+ * fluid site with value v: t = (v - offset) * scale (FP32), table entry
+ * e = clamp(floor(256 t), 0, 255) (0 for a NaN), (r, g, b, a) = lut[e] (straight
+ * alpha), composited front to back in FP32: C += (1 - A) a (r, g, b),
+ * A += (1 - A) a.  Samples in empty 4x4x4 blocks are skipped (they contribute
+ * nothing).
+ *   values  device float [N], one per site in caller order
+ *   view    host; lut: host float [256][4]
+ *   image   device float [height][width][4] = (C, A), written on the handle's stream
+ * Errors: EINVAL if the handle was created without coords, for a NULL pointer,
+ * width or height outside [1, 16384], steps outside [0, 2^24] or a non-finite
+ * scale or offset; ENOMEM; EDEVICE.  The first call builds the block map of the
+ * volume (device memory: 4 bytes per 4x4x4 block of the sites' bounding box).
+ */
+#define HEMELB_VIEW_FIX (1 << 20)
+typedef struct {
+    int64_t origin[3];
+    int64_t right[3];
+    int64_t up[3];
+    int64_t dir[3];
+    int32_t width;
+    int32_t height;
+    int32_t steps;
+    float scale;
+    float offset;
+    const float* lut;
+} hemelb_view_t;
+
+int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image);
+
+/*
  * Plain device copy of `bytes` (multiple of 16, 16-byte aligned device pointers)
  * on `stream`: the practical bandwidth ceiling and a counter calibration for
  * the stream+collide kernel.  Errors: EINVAL, EDEVICE.

@@ -1,0 +1,90 @@
+"""Direct volume rendering of a lattice property by ray marching (oracle).
+
+Section 3.C.2: the visualization keeps the voxels of a lattice property (the
+"lattice properties computed and cached" of the simulation) in a 3D texture and
+renders them with a ray-marching direct volume rendering kernel; the viewing
+parameters (zoom, rotation) and a transfer-function look-up table with a
+steerable scale and offset are the user's controls.  The paper gives no
+formulas; this is the textbook emission-absorption ray marcher (front-to-back
+"over" compositing) with the readings below, which the GPU renderer follows.
+
+* Volume: the fluid sites; site s holds value v_s at integer coordinates x_s
+  (voxel centres).  Every other point of space is empty (contributes nothing).
+* Rays: fixed-point integer vectors, F = 2^20 units per lattice spacing.  Ray
+  (i, j) starts at P0 = O + i R + j U; its samples are P_k = P0 + k D for
+  k = 0 .. K - 1.
+* Sampling: nearest voxel, x = floor((P_k + F/2) / F) on each axis.
+* Transfer: t = (v - offset) * scale in FP32; table entry e = floor(256 t)
+  clamped to [0, 255] (0 for a NaN); entry e holds (r, g, b, a), straight alpha.
+* Compositing, front to back: C <- C + (1 - A) a (r, g, b), A <- A + (1 - A) a.
+  Here in FP64 (the GPU composites in FP32).
+
+Output: image [H, W, 4] = (C, A).  Test infrastructure only.
+"""
+
+import numpy as np
+
+F = 1 << 20
+
+
+def transfer_index(values, scale, offset, entries=256):
+    """Table entries of FP32 values (the FP32 decision the renderer takes)."""
+    v = np.asarray(values, dtype=np.float32)
+    t = (v - np.float32(offset)) * np.float32(scale)
+    f = np.floor(t * np.float32(entries))
+    with np.errstate(invalid="ignore"):
+        e = np.where(f >= entries - 1, entries - 1, np.where(f > 0, f, 0))
+    e = np.where(np.isnan(f), 0, e)
+    return e.astype(np.int64)
+
+
+def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offset=0.0):
+    """Composited (r, g, b, a) [M, 4] (float64) of M rays with fixed-point start
+    points `origins` [M, 3] and sample step `direction` [3]."""
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 3)
+    lut = np.asarray(lut, dtype=np.float32).astype(np.float64)
+    P0 = np.asarray(origins, dtype=np.int64).reshape(-1, 3)
+    D = np.asarray(direction, dtype=np.int64)
+    M, K = P0.shape[0], int(steps)
+    C = np.zeros((M, 3))
+    A = np.zeros(M)
+    if coords.shape[0] == 0 or K == 0:
+        return np.concatenate([C, A[:, None]], axis=1)
+    lo = coords.min(axis=0)
+    hi = coords.max(axis=0)
+    ext = hi - lo + 1
+
+    def key(x):  # linear key of points inside the bounding box
+        return ((x[:, 0] - lo[0]) * ext[1] + (x[:, 1] - lo[1])) * ext[2] + (x[:, 2] - lo[2])
+
+    keys = key(coords)
+    order = np.argsort(keys)
+    skeys = keys[order]
+    entry = transfer_index(values, scale, offset, lut.shape[0])
+    for k in range(K):
+        x = (P0 + k * D + F // 2) >> 20  # floor division by F
+        inside = np.all((x >= lo) & (x <= hi), axis=1)
+        s = np.full(M, -1, dtype=np.int64)
+        if np.any(inside):
+            kx = key(x[inside])
+            pos = np.minimum(np.searchsorted(skeys, kx), len(skeys) - 1)
+            s[inside] = np.where(skeys[pos] == kx, order[pos], -1)
+        m = s >= 0
+        if not np.any(m):
+            continue
+        rgba = lut[entry[s[m]]]
+        a = rgba[:, 3]
+        keep = 1.0 - A[m]
+        C[m] += (keep * a)[:, None] * rgba[:, :3]
+        A[m] += keep * a
+    return np.concatenate([C, A[:, None]], axis=1)
+
+
+def render(coords, values, view, lut, scale=1.0, offset=0.0):
+    """Image [H, W, 4] (float64) of `values` at site `coords` ([N, 3] integers)."""
+    W, H, K = int(view["width"]), int(view["height"]), int(view["steps"])
+    O, R, U, D = (np.asarray(view[k], dtype=np.int64) for k in ("origin", "right", "up", "dir"))
+    jj, ii = np.meshgrid(np.arange(H, dtype=np.int64), np.arange(W, dtype=np.int64), indexing="ij")
+    P0 = O[None, :] + ii.reshape(-1, 1) * R[None, :] + jj.reshape(-1, 1) * U[None, :]
+    out = render_rays(coords, values, P0, D, K, lut, scale, offset)
+    return out.reshape(H, W, 4)

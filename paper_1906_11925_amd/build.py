@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhemelb_lb.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "adjoint.hip"),
-           os.path.join(CSRC, "host.cpp")]
+           os.path.join(CSRC, "render.hip"), os.path.join(CSRC, "host.cpp")]
 
 
 def hipcc() -> str:

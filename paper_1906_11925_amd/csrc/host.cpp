@@ -18,6 +18,7 @@
 #include "../../include/hemelb_lb.h"
 #include "adjoint.hpp"
 #include "kernels.hpp"
+#include "render.hpp"
 
 namespace {
 
@@ -184,6 +185,15 @@ struct hemelb_lb {
 
     int64_t device_bytes = 0;
 
+    // volume rendering: block map of the sites (built on the first render call)
+    std::vector<int32_t> h_coords;  // [n][3] site coordinates in Morton order (when given)
+    int32_t* r_grid = nullptr;
+    hlb::BlockRec* r_rec = nullptr;
+    float* r_vals = nullptr;
+    float* r_lut = nullptr;
+    int32_t r_blo[3] = {0, 0, 0}, r_gdim[3] = {0, 0, 0};
+    bool r_ready = false;
+
     // host copies kept for runtime updates and the adjoint
     std::vector<int32_t> order;     // Morton index -> caller index
     std::vector<int32_t> h_gsite;   // ghost link -> Morton site
@@ -281,7 +291,7 @@ void release(hemelb_lb* h) {
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
                     h->d_opart,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
-                    h->is_pend,
+                    h->is_pend,   h->r_grid,    h->r_rec,      h->r_vals,    h->r_lut,
                     h->is_lo,     h->is_hi,     h->d_vals,     h->d_basis};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -1148,6 +1158,11 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     }
     h->h_harm = P.harm;
     h->n_iolets = d->n_iolets;
+    if (d->coords) {
+        h->h_coords.resize((size_t)3 * n);
+        for (int64_t m = 0; m < n; ++m)
+            for (int a = 0; a < 3; ++a) h->h_coords[3 * m + a] = d->coords[3 * (int64_t)P.order[m] + a];
+    }
 
 #define TRY(x)              \
     do {                    \
@@ -1373,6 +1388,96 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches) {
     }
     *ms = tot;
     *launches = h->ev_used / 2;
+    return HEMELB_OK;
+}
+
+// block map of the sites for the renderer
+static int build_render_volume(hemelb_lb_t h) {
+    const int64_t n = h->n;
+    std::vector<hlb::BlockRec> rec;
+    std::vector<int32_t> bc;  // block coordinates, 3 per record
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+    uint64_t last = ~0ull;
+    for (int64_t m = 0; m < n; ++m) {
+        const int32_t* c = &h->h_coords[3 * m];
+        const uint64_t k = block_key(c[0] >> 2, c[1] >> 2, c[2] >> 2);
+        if (k != last) {
+            rec.push_back(hlb::BlockRec{0u, 0u, (int32_t)m, -1});
+            for (int a = 0; a < 3; ++a) {
+                const int32_t b = c[a] >> 2;
+                bc.push_back(b);
+                if (rec.size() == 1 || b < lo[a]) lo[a] = b;
+                if (rec.size() == 1 || b > hi[a]) hi[a] = b;
+            }
+            last = k;
+        }
+        const int p = block_pos(c[0] & 3, c[1] & 3, c[2] & 3);
+        if (p < 32)
+            rec.back().mask_lo |= 1u << p;
+        else
+            rec.back().mask_hi |= 1u << (p - 32);
+    }
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        h->r_blo[a] = (int32_t)lo[a];
+        h->r_gdim[a] = (int32_t)(hi[a] - lo[a] + 1);
+        cells *= std::max<int64_t>(0, h->r_gdim[a]);
+    }
+    if (cells > ((int64_t)1 << 31))
+        return fail(HEMELB_ENOMEM, "the sites' bounding box holds %lld blocks (at most 2^31)",
+                    (long long)cells);
+    std::vector<int32_t> grid((size_t)cells, -1);
+    for (size_t k = 0; k < rec.size(); ++k) {
+        const int64_t gx = bc[3 * k] - lo[0], gy = bc[3 * k + 1] - lo[1], gz = bc[3 * k + 2] - lo[2];
+        grid[(size_t)((gx * h->r_gdim[1] + gy) * h->r_gdim[2] + gz)] = (int32_t)k;
+    }
+    int rc;
+    if ((rc = dev_upload(h, &h->r_grid, grid, "render block map"))) return rc;
+    if ((rc = dev_upload(h, &h->r_rec, rec, "render block records"))) return rc;
+    if ((rc = dev_alloc(h, &h->r_vals, (size_t)std::max<int64_t>(n, 1), "render values"))) return rc;
+    if ((rc = dev_alloc(h, &h->r_lut, 256 * 4, "render table"))) return rc;
+    h->r_ready = true;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
+    if (!h || !view || !image || !view->lut || (!values && h->n > 0))
+        return fail(HEMELB_EINVAL, "NULL argument");
+    if (h->n > 0 && h->h_coords.empty())
+        return fail(HEMELB_EINVAL, "rendering needs the site coordinates (create with coords)");
+    if (view->width < 1 || view->width > 16384 || view->height < 1 || view->height > 16384)
+        return fail(HEMELB_EINVAL, "image size %d x %d outside [1, 16384]", view->width,
+                    view->height);
+    if (view->steps < 0 || view->steps > (1 << 24))
+        return fail(HEMELB_EINVAL, "steps %d outside [0, 2^24]", view->steps);
+    if (!std::isfinite(view->scale) || !std::isfinite(view->offset))
+        return fail(HEMELB_EINVAL, "transfer scale and offset must be finite");
+    for (int a = 0; a < 3; ++a)
+        for (const int64_t v : {view->origin[a], view->right[a], view->up[a], view->dir[a]})
+            if (v > ((int64_t)1 << 46) || v < -((int64_t)1 << 46))
+                return fail(HEMELB_EINVAL, "view vector component beyond 2^46 fixed-point units");
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    int rc;
+    if (!h->r_ready && (rc = build_render_volume(h))) return rc;
+    HIP_TRY(hlb::launch_permute(values, h->perm, h->n, h->r_vals, h->stream), "render values");
+    HIP_TRY(hipMemcpyAsync(h->r_lut, view->lut, 256 * 4 * sizeof(float), hipMemcpyHostToDevice,
+                           h->stream),
+            "render table");
+    hlb::RenderVolume V{h->r_grid, h->r_rec, h->r_vals, {h->r_blo[0], h->r_blo[1], h->r_blo[2]},
+                        {h->r_gdim[0], h->r_gdim[1], h->r_gdim[2]}};
+    hlb::RenderView v{};
+    for (int a = 0; a < 3; ++a) {
+        v.origin[a] = view->origin[a];
+        v.right[a] = view->right[a];
+        v.up[a] = view->up[a];
+        v.dir[a] = view->dir[a];
+    }
+    v.width = view->width;
+    v.height = view->height;
+    v.steps = view->steps;
+    v.scale = view->scale;
+    v.offset = view->offset;
+    HIP_TRY(hlb::launch_render(V, v, h->r_lut, image, h->stream), "render");
     return HEMELB_OK;
 }
 

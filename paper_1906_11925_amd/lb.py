@@ -203,6 +203,32 @@ class LB:
     def time(self):
         return self.info()["time"]
 
+    # -- rendering --------------------------------------------------------------
+    def render(self, values, view, lut, scale=1.0, offset=0.0, image=None):
+        """Ray-marched image [H, W, 4] (float32 CUDA tensor) of per-site `values`
+        (float32 CUDA tensor [N], caller order) seen through `view` (a dict of the
+        fixed-point vectors origin, right, up, dir and width, height, steps; see
+        include/hemelb_lb.h) with the RGBA colour table `lut` ([256, 4])."""
+        torch = _torch()
+        v = L.ViewT()
+        for name in ("origin", "right", "up", "dir"):
+            for a in range(3):
+                getattr(v, name)[a] = int(view[name][a])
+        v.width, v.height, v.steps = int(view["width"]), int(view["height"]), int(view["steps"])
+        v.scale, v.offset = float(scale), float(offset)
+        lut = np.ascontiguousarray(lut, dtype=np.float32)
+        if lut.shape != (256, 4):
+            raise ValueError("lut must be [256, 4]")
+        v.lut = _ptr(lut, L.c_float)
+        values = values.contiguous()
+        if values.dtype != torch.float32 or values.numel() != self.n or not values.is_cuda:
+            raise ValueError("values must be a float32 CUDA tensor with one entry per site")
+        if image is None:
+            image = torch.empty((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+        L.check(self.lib.hemelb_lb_render(self.h, ctypes.c_void_p(values.data_ptr()), ctypes.byref(v),
+                                          ctypes.c_void_p(image.data_ptr())))
+        return image
+
     # -- outputs -----------------------------------------------------------------
     def observables(self):
         """(p_dev [N], u [N, 3], wss [N]) float32 CUDA tensors in caller order."""

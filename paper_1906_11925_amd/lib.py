@@ -56,6 +56,15 @@ class InfoT(ctypes.Structure):
                 ("addressing", c_int32)]
 
 
+class ViewT(ctypes.Structure):
+    _fields_ = [("origin", c_int64 * 3), ("right", c_int64 * 3), ("up", c_int64 * 3),
+                ("dir", c_int64 * 3), ("width", c_int32), ("height", c_int32), ("steps", c_int32),
+                ("scale", c_float), ("offset", c_float), ("lut", P(c_float))]
+
+
+VIEW_FIX = 1 << 20
+
+
 class ObjectiveT(ctypes.Structure):
     _fields_ = [("outlet", c_int32), ("q_target", c_double), ("dome", P(ctypes.c_uint8)),
                 ("lam", c_double), ("t0", c_int64), ("t1", c_int64)]
@@ -90,6 +99,7 @@ _SIGS = {
     "hemelb_lb_kernel_timing": (c_int32, [c_void_p, c_int64]),
     "hemelb_lb_kernel_time": (c_int32, [c_void_p, P(c_double), P(c_int64)]),
     "hemelb_copy_probe": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "hemelb_lb_render": (c_int32, [c_void_p, c_void_p, P(ViewT), c_void_p]),
     "hemelb_lb_set_iolet": (c_int32, [c_void_p, c_int32, P(IoletT)]),
     "hemelb_lb_set_alpha": (c_int32, [c_void_p, P(c_float)]),
     "hemelb_lb_set_objective": (c_int32, [c_void_p, P(ObjectiveT)]),

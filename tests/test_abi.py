@@ -133,6 +133,12 @@ def test_null_handle_calls():
     assert lib.hemelb_lb_totals(None, out) == L.HEMELB_EINVAL
 
 
+def test_render_rejects_null_arguments():
+    lib = L.load()
+    v = L.ViewT()
+    assert lib.hemelb_lb_render(None, None, ctypes.byref(v), None) == L.HEMELB_EINVAL
+
+
 def test_reject_too_many_sites():
     """N >= 2^30 is rejected on the host before anything is allocated."""
     nbr = np.zeros((1, 15), dtype=np.int32)

@@ -1,0 +1,120 @@
+"""Pins of the ray-marching oracle (CPU).
+
+Each pin checks the oracle against something other than itself: the number of
+samples a ray spends in one voxel (counted by hand), the closed form of
+compositing identical samples, an independent back-to-front formulation of the
+"over" operator, exact table-entry boundaries, and symmetries of the view.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle.render import F, render, transfer_index
+from workloads.camera import axis_view, orbit_view, ramp_lut
+
+
+def _view(origin, d, right=(0, 0, 0), up=(0, 0, 0), width=1, height=1, steps=16):
+    return {"origin": list(origin), "right": list(right), "up": list(up), "dir": list(d),
+            "width": width, "height": height, "steps": steps}
+
+
+def _lut(r=0.25, g=0.5, b=1.0, a=0.125):
+    lut = np.zeros((256, 4), dtype=np.float32)
+    lut[:] = (r, g, b, a)
+    return lut
+
+
+def test_empty_volume_is_transparent():
+    img = render(np.zeros((0, 3)), np.zeros(0), _view((0, 0, 0), (F, 0, 0)), _lut())
+    assert img.shape == (1, 1, 4) and np.all(img == 0)
+
+
+def test_one_voxel_seen_by_four_samples():
+    """Samples every quarter spacing from x = -2 along +x: the nearest-voxel rule
+    puts x in [-1/2, 1/2) on the voxel at 0, i.e. samples k = 6, 7, 8, 9."""
+    view = _view((-2 * F, 0, 0), (F // 4, 0, 0), steps=16)
+    a = 0.125
+    img = render(np.array([[0, 0, 0]]), np.array([0.5]), view, _lut(a=a))
+    A = 1 - (1 - a) ** 4
+    np.testing.assert_allclose(img[0, 0], [0.25 * A, 0.5 * A, 1.0 * A, A], rtol=1e-14)
+    # steps of 3/8: the voxel covers [-1/2, 1/2), half-open
+    step = 3 * F // 8
+    cases = [(-2 * F, 3),            # offsets 1.5, 1.875, 2.25 past the start
+             (-2 * F - F // 8, 2),   # the third sample lands exactly on +1/2: next voxel
+             (-5 * F // 4, 3)]       # the first lands exactly on -1/2: this voxel
+    for start, count in cases:
+        img = render(np.array([[0, 0, 0]]), np.array([0.5]), _view((start, 0, 0), (step, 0, 0)),
+                     _lut(a=a))
+        assert img[0, 0, 3] == pytest.approx(1 - (1 - a) ** count, rel=1e-14), (start, count)
+
+
+def test_front_to_back_equals_back_to_front():
+    """A ray through a column of voxels with random values and a random table:
+    front-to-back accumulation equals the back-to-front 'over' recursion."""
+    rng = np.random.default_rng(3)
+    n = 12
+    coords = np.stack([np.arange(n), np.zeros(n, int), np.zeros(n, int)], axis=1)
+    vals = rng.uniform(0, 1, n).astype(np.float32)
+    lut = rng.uniform(0, 1, (256, 4)).astype(np.float32)
+    lut[:, 3] *= 0.3
+    view = _view((-F // 2, 0, 0), (F, 0, 0), steps=n)  # one sample per voxel
+    img = render(coords, vals, view, lut)
+    e = transfer_index(vals, 1.0, 0.0)
+    C = np.zeros(3)
+    A = 0.0
+    for k in reversed(range(n)):
+        c, a = lut[e[k], :3].astype(np.float64), float(lut[e[k], 3])
+        C = a * c + (1 - a) * C
+        A = a + (1 - a) * A
+    np.testing.assert_allclose(img[0, 0], np.r_[C, A], rtol=1e-12, atol=1e-15)
+
+
+def test_transfer_entries_at_exact_boundaries():
+    v = np.array([0.0, 1 / 256, 2 / 256 - 2 ** -20, 0.5, 255 / 256, 1.0, 7.0, -0.1, np.nan,
+                  np.inf, -np.inf], dtype=np.float32)
+    assert list(transfer_index(v, 1.0, 0.0)) == [0, 1, 1, 128, 255, 255, 255, 0, 0, 255, 0]
+    # scale and offset: t = (v - offset) * scale
+    assert list(transfer_index(np.float32([3.0, 3.5, 4.0]), 0.5, 3.0)) == [0, 64, 128]
+
+
+def test_uniform_slab_gives_uniform_image():
+    """Every ray of an axis view crosses a full slab the same number of times."""
+    g = np.mgrid[0:6, 0:5, 0:4].reshape(3, -1).T
+    vals = np.full(len(g), 0.7, dtype=np.float32)
+    view = axis_view((0, 0, 0), (5, 4, 3), axis=0, step=0.5)
+    img = render(g, vals, view, _lut(a=0.05))
+    assert img.shape == (4, 5, 4)
+    a = float(np.float32(0.05))  # the table holds FP32
+    A = 1 - (1 - a) ** 12  # 6 voxels x 2 samples each
+    np.testing.assert_allclose(img[..., 3], A, rtol=1e-14)
+
+
+def test_rotated_views_of_a_sphere_agree():
+    """A voxelised ball seen along +x and along +y (views that are exact axis
+    permutations of each other) gives the same image."""
+    r = 6
+    g = np.mgrid[-r:r + 1, -r:r + 1, -r:r + 1].reshape(3, -1).T
+    ball = g[np.sum(g * g, axis=1) <= r * r]
+    vals = (np.sqrt(np.sum(ball * ball, axis=1)) / r).astype(np.float32)
+    lut = ramp_lut(0.2)
+    vx = orbit_view((0, 0, 0), 10, 180, 0, 17, 17, pixel=1.0, step=0.5)
+    vy = orbit_view((0, 0, 0), 10, 270, 0, 17, 17, pixel=1.0, step=0.5)
+    ix = render(ball, vals, vx, lut)
+    iy = render(ball, vals, vy, lut)
+    assert ix[..., 3].max() > 0.5
+    np.testing.assert_array_equal(ix, iy)
+    # and the image of a ball is symmetric under flips of both image axes
+    np.testing.assert_allclose(ix, ix[::-1, ::-1], rtol=0, atol=1e-15)
+
+
+def test_orbit_view_geometry():
+    v = orbit_view((10, 20, 30), 50, 0, 0, 3, 2, pixel=2.0, step=0.25, steps=None)
+    assert v["dir"] == [-F // 4, 0, 0]  # looking from +x towards the centre
+    assert v["steps"] == 400
+    assert v["right"][0] == 0 and v["up"] == [0, 0, 2 * F]
+    # centre of the image plane lies `distance` before the centre
+    o = np.array(v["origin"]) + (np.array(v["right"]) * 1 + np.array(v["up"]) * 0.5)
+    np.testing.assert_allclose(o / F, [60, 20, 30], atol=1e-6)
+    assert math.isclose(np.linalg.norm(v["right"]) / F, 2.0, rel_tol=1e-6)
