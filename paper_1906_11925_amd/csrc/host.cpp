@@ -218,6 +218,7 @@ struct hemelb_lb {
     double* d_qtape = nullptr;
     double* d_wtape = nullptr;
     double* d_opart = nullptr;  // partial sums of the objective's blocks
+    int64_t obj_bytes = 0;      // device bytes of the objective's arrays
 
     // adjoint
     std::vector<void*> tape;  // K+1 population buffers of a recompute segment
@@ -986,6 +987,55 @@ int64_t planned_device_bytes(const HostPlan& P, int q, size_t elem) {
     return b;
 }
 
+// block map of the sites for the renderer
+int build_render_volume(hemelb_lb_t h) {
+    const int64_t n = h->n;
+    std::vector<hlb::BlockRec> rec;
+    std::vector<int32_t> bc;  // block coordinates, 3 per record
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+    uint64_t last = ~0ull;
+    for (int64_t m = 0; m < n; ++m) {
+        const int32_t* c = &h->h_coords[3 * m];
+        const uint64_t k = block_key(c[0] >> 2, c[1] >> 2, c[2] >> 2);
+        if (k != last) {
+            rec.push_back(hlb::BlockRec{0u, 0u, (int32_t)m, -1});
+            for (int a = 0; a < 3; ++a) {
+                const int32_t b = c[a] >> 2;
+                bc.push_back(b);
+                if (rec.size() == 1 || b < lo[a]) lo[a] = b;
+                if (rec.size() == 1 || b > hi[a]) hi[a] = b;
+            }
+            last = k;
+        }
+        const int p = block_pos(c[0] & 3, c[1] & 3, c[2] & 3);
+        if (p < 32)
+            rec.back().mask_lo |= 1u << p;
+        else
+            rec.back().mask_hi |= 1u << (p - 32);
+    }
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        h->r_blo[a] = (int32_t)lo[a];
+        h->r_gdim[a] = (int32_t)(hi[a] - lo[a] + 1);
+        cells *= std::max<int64_t>(0, h->r_gdim[a]);
+    }
+    if (cells > ((int64_t)1 << 31))
+        return fail(HEMELB_ENOMEM, "the sites' bounding box holds %lld blocks (at most 2^31)",
+                    (long long)cells);
+    std::vector<int32_t> grid((size_t)cells, -1);
+    for (size_t k = 0; k < rec.size(); ++k) {
+        const int64_t gx = bc[3 * k] - lo[0], gy = bc[3 * k + 1] - lo[1], gz = bc[3 * k + 2] - lo[2];
+        grid[(size_t)((gx * h->r_gdim[1] + gy) * h->r_gdim[2] + gz)] = (int32_t)k;
+    }
+    int rc;
+    if ((rc = dev_upload(h, &h->r_grid, grid, "render block map"))) return rc;
+    if ((rc = dev_upload(h, &h->r_rec, rec, "render block records"))) return rc;
+    if ((rc = dev_alloc(h, &h->r_vals, (size_t)std::max<int64_t>(n, 1), "render values"))) return rc;
+    if ((rc = dev_alloc(h, &h->r_lut, 256 * 4, "render table"))) return rc;
+    h->r_ready = true;
+    return HEMELB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1391,55 +1441,6 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches) {
     return HEMELB_OK;
 }
 
-// block map of the sites for the renderer
-static int build_render_volume(hemelb_lb_t h) {
-    const int64_t n = h->n;
-    std::vector<hlb::BlockRec> rec;
-    std::vector<int32_t> bc;  // block coordinates, 3 per record
-    int64_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
-    uint64_t last = ~0ull;
-    for (int64_t m = 0; m < n; ++m) {
-        const int32_t* c = &h->h_coords[3 * m];
-        const uint64_t k = block_key(c[0] >> 2, c[1] >> 2, c[2] >> 2);
-        if (k != last) {
-            rec.push_back(hlb::BlockRec{0u, 0u, (int32_t)m, -1});
-            for (int a = 0; a < 3; ++a) {
-                const int32_t b = c[a] >> 2;
-                bc.push_back(b);
-                if (rec.size() == 1 || b < lo[a]) lo[a] = b;
-                if (rec.size() == 1 || b > hi[a]) hi[a] = b;
-            }
-            last = k;
-        }
-        const int p = block_pos(c[0] & 3, c[1] & 3, c[2] & 3);
-        if (p < 32)
-            rec.back().mask_lo |= 1u << p;
-        else
-            rec.back().mask_hi |= 1u << (p - 32);
-    }
-    int64_t cells = 1;
-    for (int a = 0; a < 3; ++a) {
-        h->r_blo[a] = (int32_t)lo[a];
-        h->r_gdim[a] = (int32_t)(hi[a] - lo[a] + 1);
-        cells *= std::max<int64_t>(0, h->r_gdim[a]);
-    }
-    if (cells > ((int64_t)1 << 31))
-        return fail(HEMELB_ENOMEM, "the sites' bounding box holds %lld blocks (at most 2^31)",
-                    (long long)cells);
-    std::vector<int32_t> grid((size_t)cells, -1);
-    for (size_t k = 0; k < rec.size(); ++k) {
-        const int64_t gx = bc[3 * k] - lo[0], gy = bc[3 * k + 1] - lo[1], gz = bc[3 * k + 2] - lo[2];
-        grid[(size_t)((gx * h->r_gdim[1] + gy) * h->r_gdim[2] + gz)] = (int32_t)k;
-    }
-    int rc;
-    if ((rc = dev_upload(h, &h->r_grid, grid, "render block map"))) return rc;
-    if ((rc = dev_upload(h, &h->r_rec, rec, "render block records"))) return rc;
-    if ((rc = dev_alloc(h, &h->r_vals, (size_t)std::max<int64_t>(n, 1), "render values"))) return rc;
-    if ((rc = dev_alloc(h, &h->r_lut, 256 * 4, "render table"))) return rc;
-    h->r_ready = true;
-    return HEMELB_OK;
-}
-
 int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
     if (!h || !view || !image || !view->lut || (!values && h->n > 0))
         return fail(HEMELB_EINVAL, "NULL argument");
@@ -1553,6 +1554,8 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
             (void)hipFree(*p);
             *p = nullptr;
         }
+    h->device_bytes -= h->obj_bytes;
+    h->obj_bytes = 0;
     h->obj_set = false;
     h->adj_t = -1;
     if (!obj) return HEMELB_OK;
@@ -1577,6 +1580,7 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
     }
     const size_t nw = (size_t)std::max<int64_t>(1, obj->t1 - obj->t0);
     int rc;
+    const int64_t before = h->device_bytes;
     if ((rc = dev_upload(h, &h->d_out_links, outl, "objective links"))) return rc;
     if ((rc = dev_upload(h, &h->d_dome, dome, "objective dome"))) return rc;
     if ((rc = dev_upload(h, &h->d_wss_w, w, "objective weights"))) return rc;
@@ -1586,6 +1590,7 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
     if ((rc = dev_upload(h, &h->d_opart, parts, "objective partials"))) return rc;
     if ((rc = dev_upload(h, &h->d_qtape, zeros, "flux tape"))) return rc;
     if ((rc = dev_upload(h, &h->d_wtape, zeros, "shear tape"))) return rc;
+    h->obj_bytes = h->device_bytes - before;
     h->n_out = (int32_t)outl.size();
     h->n_dome = (int64_t)dome.size();
     h->obj_outlet = obj->outlet;

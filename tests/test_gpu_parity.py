@@ -141,6 +141,20 @@ def test_one_step_f32_elementwise(name, q):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
+def _tol16(o, ref, f, storage, q):
+    """Bound on one 16-bit step (see test_one_step_16bit_elementwise): the output
+    rounding, FP32 collision error, and the rounding of the incoming iolet values
+    at iolet sites.  Returns (bound, bound without the iolet term, sites without
+    iolet links)."""
+    ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
+    s = SCALES[q][:, None]
+    sub = 2.0 ** -25 / s if storage == "f16" else 0.0 * s
+    ghost = o.links.kind == 2
+    g_err = np.where(ghost, ulp * np.abs(f - o.lat.w[:, None]) + sub, 0.0).sum(axis=0)
+    plain_tol = ulp * np.abs(ref) + sub + fp32_tol(q, 1e-3)
+    return plain_tol + 3.0 * g_err[None, :], plain_tol, ~ghost.any(axis=0)
+
+
 def test_one_step_16bit_elementwise(storage):
     """16-bit storage: the input is exact, one FP32 collision follows, then one
     rounding of d * scale (relative half-ulp 2^-11 for FP16, 2^-8 for BF16).
@@ -159,16 +173,10 @@ def test_one_step_16bit_elementwise(storage):
     lb.close()
     A, f = o.step(o.lat.w[:, None] + d, 37)
     ref = A - o.lat.w[:, None]
-    ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
-    s = SCALES[q][:, None]
-    sub = 2.0 ** -25 / s if storage == "f16" else 0.0 * s
-    ghost = o.links.kind == 2
-    g_err = np.where(ghost, ulp * np.abs(f - o.lat.w[:, None]) + sub, 0.0).sum(axis=0)
-    tol = ulp * np.abs(ref) + sub + fp32_tol(q, 1e-3) + 3.0 * g_err[None, :]
+    tol, plain_tol, plain = _tol16(o, ref, f, storage, q)
     assert np.all(np.abs(gpu - ref) <= tol)
     # away from iolets the bound is the plain rounding bound
-    plain = ~ghost.any(axis=0)
-    assert np.all(np.abs(gpu - ref)[:, plain] <= (ulp * np.abs(ref) + sub + fp32_tol(q, 1e-3))[:, plain])
+    assert np.all(np.abs(gpu - ref)[:, plain] <= plain_tol[:, plain])
 
 
 def test_one_step_brinkman_alpha():
@@ -385,9 +393,55 @@ def test_full_size_one_step(name):
     assert np.abs(u - ou).max() < fp32_tol(15, 1e-3)
 
 
+@pytest.mark.parametrize("name", ["aneurysm", "tree1024"])
+def test_full_size_one_step_16bit_blocks(name):
+    """The FP16 form the benchmark times (block addressing) on the full-size
+    workloads: one step from a random state, element by element, to the 16-bit
+    bound."""
+    _gpu()
+    q, storage = 15, "f16"
+    g = wl.config_geometry(name)
+    o = LBGK(g, q)
+    d = quantize(wl.random_deviations(q, o.n, 13, 1e-3), q, storage)
+    lb = LB.from_geometry(g, lattice=q, storage=storage)
+    assert lb.info()["addressing"] == L.ADDR_BLOCKS
+    lb.set_deviations(torch.from_numpy(d), t=37)
+    lb.step(1)
+    gpu = _dev(lb)
+    lb.close()
+    A, f = o.step(o.lat.w[:, None] + d, 37)
+    ref = A - o.lat.w[:, None]
+    tol, _, _ = _tol16(o, ref, f, storage, q)
+    print(f"{name} f16 blocks: {o.n} sites, worst |err|/tol {np.max(np.abs(gpu - ref) / tol):.3f}",
+          flush=True)
+    assert np.all(np.abs(gpu - ref) <= tol)
+
+
 @pytest.fixture(scope="module")
 def tree2048():
     return wl.config_geometry("tree2048")
+
+
+@pytest.mark.parametrize("q", [15, 19])
+def test_tree2048_one_step_sampled_16bit_blocks(tree2048, q):
+    """The largest workload in FP16 storage with block addressing: one step,
+    compared with the oracle's sampled step at 20,000 random sites."""
+    _gpu()
+    g = tree2048
+    n = g.n_sites
+    d = quantize(wl.random_deviations(q, n, 19, 1e-3), q, "f16")
+    lb = LB.from_geometry(g, lattice=q, storage="f16")
+    assert lb.info()["addressing"] == L.ADDR_BLOCKS
+    lb.set_deviations(torch.from_numpy(d.astype(np.float32)), t=11)
+    lb.step(1)
+    sites = np.sort(np.random.default_rng(6).choice(n, 20000, replace=False))
+    gpu = lb.get_deviations()[:, torch.from_numpy(sites).cuda()].cpu().numpy().astype(np.float64)
+    lb.close()
+    o = LBGK(g, q, sites=sites)
+    A, f = o.step(o.lat.w[:, None] + d.astype(np.float64), 11)
+    ref = A - o.lat.w[:, None]
+    tol, _, _ = _tol16(o, ref, f, "f16", q)
+    assert np.all(np.abs(gpu - ref) <= tol)
 
 
 @pytest.mark.parametrize("q", [15, 19])
