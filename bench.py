@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fluid-site updates/s (GLUPS) + % HBM peak, FP32 vs FP16-store; adjoint GLUPS"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11925_amd", "csrc", f)
-               for f in ("kernels.hip", "kernels.hpp", "lbdev.hpp", "lattice.hpp")]
+               for f in ("kernels.hip", "kernels.hpp", "step.hpp", "lbdev.hpp", "lattice.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -187,8 +187,7 @@ def adjoint_run(steps=4000, K=200, window=1000):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lb.adjoint_begin(K)
-    for s0, k, ck in reversed(cks):
-        lb.adjoint_segment(ck, s0, k)
+    lb.adjoint_run(cks)  # recompute of segment k-1 overlaps the reverse of segment k
     th, da = lb.adjoint_grads()
     t_bwd = time.perf_counter() - t0
     lb.close()

@@ -407,6 +407,20 @@ int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment);
 int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps);
 
 /*
+ * The whole reverse sweep over nseg segments given in forward order (host arrays:
+ * checkpoints[k] is the device raw state at time t0[k], segment k covers steps
+ * t0[k] .. t0[k]+steps[k]-1, consecutive segments join and the last ends at the
+ * time the sweep has reached).  The result is that of calling
+ * hemelb_lb_adjoint_segment for k = nseg-1 .. 0, bit for bit; each adjoint step
+ * of segment k runs in one launch with a recompute step of segment k-1 (a second
+ * tape, allocated on first use), so the sweep takes about one launch per time
+ * step instead of two.  Asynchronous on the handle's stream.
+ * Errors: EORDER, EINVAL, ENOMEM.
+ */
+int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
+                          const int64_t* steps, int64_t nseg);
+
+/*
  * Gradients accumulated so far (waits).  dtheta: host doubles, for every velocity
  * iolet in id order its 1 + 2 n_harm derivatives (mean, cos_1..n, sin_1..n);
  * dalpha: host doubles [N] caller order.  Either may be NULL.  Errors: EORDER.

@@ -49,8 +49,7 @@ class LBAdjointFn(torch.autograd.Function):
     def backward(ctx, gJ):
         lb = ctx.lb
         lb.adjoint_begin(ctx.K)
-        for t0, k, ck in reversed(ctx.checkpoints):
-            lb.adjoint_segment(ck, t0, k)
+        lb.adjoint_run(ctx.checkpoints)
         dth, da = lb.adjoint_grads()
         g = float(gJ)
         dtheta = torch.from_numpy(dth[ctx.inlet] * g)

@@ -36,6 +36,7 @@
 #include "kernels.hpp"
 #include "lattice.hpp"
 #include "lbdev.hpp"
+#include "step.hpp"
 
 namespace hlb {
 
@@ -241,17 +242,17 @@ __device__ inline void iolet_adjoint(const typename Store<ST>::T* __restrict__ A
 // ---------------------------------------------------------------------------
 // reverse step: transposed collision + push along the forward's pull addresses
 // ---------------------------------------------------------------------------
+// The reverse step of one workgroup (group grp of four tiles).  Every thread of
+// the workgroup calls it.
 template <int Q, int ST, bool SC, bool BRINK>
-__global__ __launch_bounds__(kBlock) void k_adj_scatter(
+__device__ inline void adj_scatter_group(
     const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
-    float* __restrict__ gout, Table tb, int32_t n, float omega,
+    float* __restrict__ gout, const Table& tb, int32_t n, float omega,
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
-    const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
+    const float* __restrict__ wss_w, const float* __restrict__ normal, const Ghosts& G,
+    const IoletAdj& I, int32_t grp, StageLds& lds) {
     using Lt = Lat<Q>;
-    using C = Codec<Q, ST, SC>;
     static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
-    __shared__ StageLds lds;
-    const int32_t grp = blockIdx.x;
     const int32_t s = grp * kBlock + threadIdx.x;
     const bool live = (s & ~(kTile - 1)) < n;
     float d[Q];
@@ -349,6 +350,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
     if (kis >= 0) iolet_adjoint<Q, ST, SC>(A, s, j, fh, G, I, kis, n);
 }
 
+template <int Q, int ST, bool SC, bool BRINK>
+__global__ __launch_bounds__(kBlock) void k_adj_scatter(
+    const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
+    float* __restrict__ gout, Table tb, int32_t n, float omega,
+    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
+    const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
+    __shared__ StageLds lds;
+    adj_scatter_group<Q, ST, SC, BRINK>(A, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w, normal,
+                                        G, I, (int32_t)blockIdx.x, lds);
+}
+
+// A recompute step of one segment (blocks below nb_fwd) and a reverse step of
+// the next later segment (the other blocks) in one launch: the two touch disjoint
+// buffers, and for a lattice too small to fill the GPU each half runs beside the
+// other instead of after it.
+template <int Q, int ST, bool SC, bool BRINK>
+__global__ __launch_bounds__(kBlock) void k_adj_dual(
+    const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
+    Ghosts Gf, int64_t t_next, int32_t nb_fwd, const typename Store<ST>::T* __restrict__ A,
+    const float* __restrict__ gin, float* __restrict__ gout, Table tb, int32_t n, float omega,
+    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
+    const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
+    __shared__ StageLds lds;
+    if ((int32_t)blockIdx.x < nb_fwd)
+        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, (int32_t)blockIdx.x, omega,
+                                                      alpha, Gf, t_next, lds);
+    else
+        adj_scatter_group<Q, ST, SC, BRINK>(A, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
+                                            normal, G, I, (int32_t)blockIdx.x - nb_fwd, lds);
+}
+
 // adds what the last reverse step left pending to the sites' own populations
 template <int Q>
 __global__ __launch_bounds__(kBlock) void k_adj_flush(float* __restrict__ gout, IoletAdj I) {
@@ -402,6 +434,30 @@ hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, 
                 wss_w, normal, G, I);
         else
             k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, false><<<blocks(L.n), kBlock, 0, s>>>(
+                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
+                alpha_hat, wss_w, normal, G, I);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_dual(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
+                           int64_t t_next, const Ghosts& G, const IoletAdj& I, const void* A,
+                           const float* gin, float* gout, float omega, const float* alpha,
+                           double* alpha_hat, const float* wss_w, const float* normal,
+                           hipStream_t s) {
+    if (L.n == 0) return hipSuccess;
+    const int32_t nb = (int32_t)blocks(L.n);
+    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        if (alpha)
+            k_adj_dual<Tg::Q, Tg::ST, Tg::SC, true><<<2u * nb, kBlock, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, nb,
+                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, alpha, alpha_hat,
+                wss_w, normal, G, I);
+        else
+            k_adj_dual<Tg::Q, Tg::ST, Tg::SC, false><<<2u * nb, kBlock, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, nb,
                 static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
                 alpha_hat, wss_w, normal, G, I);
         return hipGetLastError();

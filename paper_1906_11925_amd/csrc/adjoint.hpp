@@ -57,4 +57,12 @@ hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, 
                            hipStream_t s);
 hipError_t launch_adj_flush(int q, float* gout, const IoletAdj& I, hipStream_t s);
 
+// One launch of two independent steps: the recompute step src -> dst at t_next
+// (ghosts Gf) and the reverse step of launch_adj_step (no interpolated walls).
+hipError_t launch_adj_dual(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
+                           int64_t t_next, const Ghosts& G, const IoletAdj& I, const void* A,
+                           const float* gin, float* gout, float omega, const float* alpha,
+                           double* alpha_hat, const float* wss_w, const float* normal,
+                           hipStream_t s);
+
 }  // namespace hlb

@@ -162,9 +162,7 @@ struct hemelb_lb {
     double* d_vals = nullptr;  // iolet values for a batch of steps
     int64_t vals_cap = 0;      // steps the buffer holds
     int64_t vals_t0 = 0;
-    double* d_basis = nullptr;  // Fourier basis of velocity iolets per step (adjoint)
-    int64_t basis_cap = 0;      // steps the buffer holds
-    int32_t basis_stride = 0;   // doubles per (step, iolet): 2 x the most harmonics
+    int32_t basis_stride = 0;   // Fourier basis doubles per (step, iolet): 2 x the most harmonics
     int32_t* perm = nullptr;  // Morton index -> caller index (null: identity)
     float* normal = nullptr;  // [3][n] Morton order
     float* alpha = nullptr;
@@ -222,6 +220,13 @@ struct hemelb_lb {
 
     // adjoint
     std::vector<void*> tape;  // K+1 population buffers of a recompute segment
+    std::vector<void*> tape2;  // a second tape: recompute one segment while reversing another
+    struct Series {            // iolet values and Fourier basis of one segment
+        double* vals = nullptr;
+        double* basis = nullptr;
+        int64_t cap = 0, t0 = 0;
+        int32_t stride = 0;    // basis doubles per (step, iolet) the buffer was sized for
+    } series[2];
     float* ghat[2] = {nullptr, nullptr};
     int gcur = 0;
     double* alpha_hat = nullptr;
@@ -243,9 +248,9 @@ struct hemelb_lb {
                            bfl};
     }
     hlb::Ghosts ghosts() const {
-        return hlb::Ghosts{nghost,  g_slot,  g_cell_link, g_site,   g_dir,   g_iolet,
-                           g_coef,  d_iolets, d_harm,     d_vals,   vals_t0, n_iolets,
-                           d_basis, basis_stride};
+        return hlb::Ghosts{nghost,  g_slot,   g_cell_link, g_site,  g_dir,   g_iolet,
+                           g_coef,  d_iolets, d_harm,      d_vals,  vals_t0, n_iolets,
+                           nullptr, basis_stride};
     }
     size_t elem() const { return storage == HEMELB_STORE_F32 ? 4 : 2; }
     // algorithmic HBM bytes of one site update: populations read and written once,
@@ -293,11 +298,17 @@ void release(hemelb_lb* h) {
                     h->d_opart,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
                     h->is_pend,   h->r_grid,    h->r_rec,      h->r_vals,    h->r_lut,
-                    h->is_lo,     h->is_hi,     h->d_vals,     h->d_basis};
+                    h->is_lo,     h->is_hi,     h->d_vals};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (void* p : h->tape)
         if (p) (void)hipFree(p);
+    for (void* p : h->tape2)
+        if (p) (void)hipFree(p);
+    for (auto& sr : h->series) {
+        if (sr.vals) (void)hipFree(sr.vals);
+        if (sr.basis) (void)hipFree(sr.basis);
+    }
     for (auto e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }
@@ -672,23 +683,9 @@ bool build_blocks(const hemelb_lb_desc_t* d, const HostLat& lat, const std::vect
     return true;
 }
 
-// iolet values (and with `basis` the velocity iolets' Fourier basis) for times
-// t0 .. t0 + count - 1 into the handle's tables
-int fill_series(hemelb_lb* h, int64_t t0, int64_t count, bool basis = false) {
+// iolet values for times t0 .. t0 + count - 1 into the handle's table
+int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
     if (h->n_iolets == 0) return HEMELB_OK;
-    basis = basis && h->basis_stride > 0;
-    if (basis && count > h->basis_cap) {
-        HIP_TRY(hipStreamSynchronize(h->stream), "sync");
-        if (h->d_basis) {
-            (void)hipFree(h->d_basis);
-            h->device_bytes -= h->basis_cap * h->n_iolets * h->basis_stride * (int64_t)sizeof(double);
-            h->d_basis = nullptr;
-        }
-        int rc = dev_alloc(h, &h->d_basis, (size_t)(count * h->n_iolets * h->basis_stride),
-                           "iolet basis");
-        if (rc) return rc;
-        h->basis_cap = count;
-    }
     if (count > h->vals_cap) {
         HIP_TRY(hipStreamSynchronize(h->stream), "sync");
         if (h->d_vals) {
@@ -702,7 +699,7 @@ int fill_series(hemelb_lb* h, int64_t t0, int64_t count, bool basis = false) {
         h->vals_cap = cap;
     }
     HIP_TRY(hlb::launch_iolet_series(h->d_iolets, h->d_harm, h->n_iolets, t0, count, h->d_vals,
-                                     basis ? h->d_basis : nullptr, h->basis_stride, h->stream),
+                                     nullptr, 0, h->stream),
             "iolet series");
     h->vals_t0 = t0;
     return HEMELB_OK;
@@ -1033,6 +1030,120 @@ int build_render_volume(hemelb_lb_t h) {
     if ((rc = dev_alloc(h, &h->r_vals, (size_t)std::max<int64_t>(n, 1), "render values"))) return rc;
     if ((rc = dev_alloc(h, &h->r_lut, 256 * 4, "render table"))) return rc;
     h->r_ready = true;
+    return HEMELB_OK;
+}
+
+// iolet values (and the Fourier basis of velocity iolets) for times t0 .. t0 + count
+// - 1 into the series buffers `sr`, on `stream`
+int fill_segment_series(hemelb_lb* h, hemelb_lb::Series& sr, int64_t t0, int64_t count,
+                        hipStream_t stream) {
+    if (h->n_iolets == 0) return HEMELB_OK;
+    if (count > sr.cap || h->basis_stride > sr.stride) {
+        HIP_TRY(hipDeviceSynchronize(), "sync");  // no queued work may still use the buffers
+        if (sr.vals) (void)hipFree(sr.vals);
+        if (sr.basis) (void)hipFree(sr.basis);
+        h->device_bytes -= sr.cap * h->n_iolets * (1 + sr.stride) * (int64_t)sizeof(double);
+        sr.vals = sr.basis = nullptr;
+        sr.cap = 0;
+        sr.stride = 0;
+        int rc = dev_alloc(h, &sr.vals, (size_t)(count * h->n_iolets), "segment iolet values");
+        if (rc) return rc;
+        if (h->basis_stride > 0 &&
+            (rc = dev_alloc(h, &sr.basis, (size_t)(count * h->n_iolets * h->basis_stride),
+                            "segment iolet basis")))
+            return rc;
+        sr.cap = count;
+        sr.stride = h->basis_stride;
+    }
+    HIP_TRY(hlb::launch_iolet_series(h->d_iolets, h->d_harm, h->n_iolets, t0, count, sr.vals,
+                                     sr.basis, h->basis_stride, stream),
+            "iolet series");
+    sr.t0 = t0;
+    return HEMELB_OK;
+}
+
+hlb::Ghosts segment_ghosts(const hemelb_lb* h, const hemelb_lb::Series& sr) {
+    hlb::Ghosts G = h->ghosts();
+    G.vals = sr.vals;
+    G.vals_t0 = sr.t0;
+    G.basis = sr.basis;
+    return G;
+}
+
+// restore `checkpoint` into tape[0] for a recompute from time t0 (series for
+// `steps` steps)
+int begin_recompute(hemelb_lb* h, std::vector<void*>& tape, hemelb_lb::Series& sr,
+                    const void* checkpoint, int64_t t0, int64_t steps, hipStream_t stream) {
+    int rc = fill_segment_series(h, sr, t0, steps + 1, stream);
+    if (rc) return rc;
+    HIP_TRY(hlb::launch_state(h->layout(), tape[0], const_cast<void*>(checkpoint), h->perm, 1,
+                              stream),
+            "checkpoint restore");
+    return HEMELB_OK;
+}
+
+// recompute step m of the segment starting at t0: tape[m] -> tape[m + 1]
+int recompute_step(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
+                   int64_t m, hipStream_t stream) {
+    const hlb::Layout L = h->layout();
+    const hlb::Ghosts G = segment_ghosts(h, sr);
+    if (m == 0 || !hlb::ghosts_fused())
+        HIP_TRY(hlb::launch_ghost_fill(L, G, tape[m], t0 + m, stream), "recompute ghosts");
+    HIP_TRY(hlb::launch_stream_collide(L, G, tape[m], tape[m + 1], h->omega, h->alpha, h->xcd_group,
+                                       t0 + m + 1, stream),
+            "recompute");
+    return HEMELB_OK;
+}
+
+// iolet terms of the reverse step at time t
+hlb::IoletAdj iolet_adj(const hemelb_lb* h, int64_t t) {
+    const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
+    const bool inw = t >= h->w0 && t < h->w1;
+    return hlb::IoletAdj{S,          h->is_link,        h->is_pend,  (double)t,     h->obj_outlet,
+                         h->d_qtape, inw ? t - h->w0 : -1, h->q_target, h->theta_acc, h->nbasis};
+}
+
+// objective weights of the reverse step at time t (null outside the window)
+const float* wss_weights(const hemelb_lb* h, int64_t t) {
+    return t >= h->w0 && t < h->w1 ? h->d_wss_w : nullptr;
+}
+
+// reverse step t0 + m from the recomputed tape
+int reverse_step(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
+                 int64_t m, hipStream_t stream) {
+    const int64_t t = t0 + m;
+    HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t), tape[m],
+                                 h->ghat[h->gcur], h->ghat[h->gcur ^ 1], h->omega, h->alpha,
+                                 h->alpha_hat, wss_weights(h, t), h->normal, stream),
+            "adjoint step");
+    h->gcur ^= 1;
+    return HEMELB_OK;
+}
+
+// recompute step mf of the segment at tf0 (tape tf, series sf) and reverse step
+// mr of the segment at tr0 (tape tr, series sr) in one launch
+int dual_step(hemelb_lb* h, std::vector<void*>& tf, const hemelb_lb::Series& sf, int64_t tf0,
+              int64_t mf, std::vector<void*>& tr, const hemelb_lb::Series& sr, int64_t tr0,
+              int64_t mr, hipStream_t stream) {
+    const hlb::Layout L = h->layout();
+    const hlb::Ghosts Gf = segment_ghosts(h, sf);
+    if (mf == 0 || !hlb::ghosts_fused())
+        HIP_TRY(hlb::launch_ghost_fill(L, Gf, tf[mf], tf0 + mf, stream), "recompute ghosts");
+    const int64_t t = tr0 + mr;
+    HIP_TRY(hlb::launch_adj_dual(L, Gf, tf[mf], tf[mf + 1], tf0 + mf + 1, segment_ghosts(h, sr),
+                                 iolet_adj(h, t), tr[mr], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
+                                 h->omega, h->alpha, h->alpha_hat, wss_weights(h, t), h->normal,
+                                 stream),
+            "adjoint dual step");
+    h->gcur ^= 1;
+    return HEMELB_OK;
+}
+
+// the iolet terms still pending after the last reverse step of a segment
+int end_reverse(hemelb_lb* h, hipStream_t stream) {
+    const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
+    const hlb::IoletAdj I{S, h->is_link, h->is_pend, 0.0, -1, nullptr, -1, 0.0, nullptr, 0};
+    HIP_TRY(hlb::launch_adj_flush(h->q, h->ghat[h->gcur], I, stream), "adjoint flush");
     return HEMELB_OK;
 }
 
@@ -1707,36 +1818,77 @@ int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0,
                     (long long)h->adj_t);
     if (!checkpoint && h->n > 0) return fail(HEMELB_EINVAL, "checkpoint is NULL");
     HIP_TRY(hipSetDevice(h->device), "set device");
-    int rc = fill_series(h, t0, steps + 1, true);
+    h->ghosts_ready = false;
+    int rc = begin_recompute(h, h->tape, h->series[0], checkpoint, t0, steps, h->stream);
+    for (int64_t m = 0; m < steps && !rc; ++m) rc = recompute_step(h, h->tape, h->series[0], t0, m, h->stream);
+    for (int64_t m = steps - 1; m >= 0 && !rc; --m)
+        rc = reverse_step(h, h->tape, h->series[0], t0, m, h->stream);
+    if (!rc) rc = end_reverse(h, h->stream);
     if (rc) return rc;
-    h->ghosts_ready = false;  // the forward's values table is overwritten
-    const hlb::Layout L = h->layout();
-    const hlb::Ghosts G = h->ghosts();
-    HIP_TRY(hlb::launch_state(L, h->tape[0], const_cast<void*>(checkpoint), h->perm, 1, h->stream),
-            "checkpoint restore");
-    for (int64_t m = 0; m < steps; ++m) {
-        if (m == 0 || !hlb::ghosts_fused())
-            HIP_TRY(hlb::launch_ghost_fill(L, G, h->tape[m], t0 + m, h->stream), "recompute ghosts");
-        HIP_TRY(hlb::launch_stream_collide(L, G, h->tape[m], h->tape[m + 1], h->omega, h->alpha,
-                                           h->xcd_group, t0 + m + 1, h->stream),
-                "recompute");
-    }
-    const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
-    hlb::IoletAdj I{S,          h->is_link,  h->is_pend,     0.0,      h->obj_outlet,
-                    h->d_qtape, -1,          h->q_target,    h->theta_acc, h->nbasis};
-    for (int64_t m = steps - 1; m >= 0; --m) {
-        const int64_t t = t0 + m;
-        const bool inw = t >= h->w0 && t < h->w1;
-        I.t = (double)t;
-        I.q_index = inw ? t - h->w0 : -1;
-        HIP_TRY(hlb::launch_adj_step(L, G, I, h->tape[m], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
-                                     h->omega, h->alpha, h->alpha_hat, inw ? h->d_wss_w : nullptr,
-                                     h->normal, h->stream),
-                "adjoint step");
-        h->gcur ^= 1;
-    }
-    HIP_TRY(hlb::launch_adj_flush(h->q, h->ghat[h->gcur], I, h->stream), "adjoint flush");
     h->adj_t = t0;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
+                          const int64_t* steps, int64_t nseg) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (h->adj_t < 0) return fail(HEMELB_EORDER, "call hemelb_lb_adjoint_begin first");
+    if (nseg < 0 || (nseg > 0 && (!checkpoints || !t0 || !steps)))
+        return fail(HEMELB_EINVAL, "NULL segment arrays");
+    if (nseg == 0) return HEMELB_OK;
+    for (int64_t k = 0; k < nseg; ++k) {
+        if (steps[k] < 1 || steps[k] + 1 > (int64_t)h->tape.size())
+            return fail(HEMELB_EINVAL, "segment %lld of %lld steps exceeds the tape (%lld)",
+                        (long long)k, (long long)steps[k], (long long)h->tape.size() - 1);
+        if (!checkpoints[k] && h->n > 0) return fail(HEMELB_EINVAL, "checkpoint %lld is NULL", (long long)k);
+        const int64_t end = k + 1 < nseg ? t0[k + 1] : h->adj_t;
+        if (t0[k] < 0 || t0[k] + steps[k] != end)
+            return fail(HEMELB_EORDER, "segment %lld must end where the next one starts (%lld)",
+                        (long long)k, (long long)end);
+    }
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    h->ghosts_ready = false;
+    const size_t popbytes = (size_t)h->q * h->slots * h->elem();
+    while (h->tape2.size() < h->tape.size()) {
+        void* p = nullptr;
+        HIP_TRY(hipMalloc(&p, popbytes), "adjoint tape");
+        h->tape2.push_back(p);
+        h->device_bytes += (int64_t)popbytes;
+    }
+    std::vector<void*>* tapes[2] = {&h->tape, &h->tape2};
+    // Segment k is recomputed into tape (nseg - 1 - k) & 1.  The reverse steps of
+    // segment k pair with the recompute steps of segment k - 1 (the other tape and
+    // series buffer): each pair is one launch, so a lattice too small to fill the
+    // GPU keeps it busy with both, at half the launches.  One stream orders
+    // everything, so results are those of the segments run one after another.
+    int rc = begin_recompute(h, *tapes[0], h->series[0], checkpoints[nseg - 1], t0[nseg - 1],
+                             steps[nseg - 1], h->stream);
+    for (int64_t m = 0; m < steps[nseg - 1] && !rc; ++m)
+        rc = recompute_step(h, *tapes[0], h->series[0], t0[nseg - 1], m, h->stream);
+    if (rc) return rc;
+    for (int64_t i = 0; i < nseg; ++i) {
+        const int64_t k = nseg - 1 - i;
+        const int b = (int)(i & 1), nb = b ^ 1;
+        std::vector<void*>& tr = *tapes[b];
+        std::vector<void*>& tf = *tapes[nb];
+        const int64_t nr = k > 0 ? steps[k - 1] : 0;
+        if (k > 0 && (rc = begin_recompute(h, tf, h->series[nb], checkpoints[k - 1], t0[k - 1],
+                                           nr, h->stream)))
+            return rc;
+        for (int64_t m = 0; m < std::max(steps[k], nr); ++m) {
+            const int64_t mr = steps[k] - 1 - m;
+            if (m < steps[k] && m < nr)
+                rc = dual_step(h, tf, h->series[nb], t0[k - 1], m, tr, h->series[b], t0[k], mr,
+                               h->stream);
+            else if (m < steps[k])
+                rc = reverse_step(h, tr, h->series[b], t0[k], mr, h->stream);
+            else
+                rc = recompute_step(h, tf, h->series[nb], t0[k - 1], m, h->stream);
+            if (rc) return rc;
+        }
+        if ((rc = end_reverse(h, h->stream))) return rc;
+    }
+    h->adj_t = t0[0];
     return HEMELB_OK;
 }
 

@@ -1,0 +1,178 @@
+// The fused pull-stream + LBGK-collide step of one site and one workgroup, shared
+// by the step kernel and the adjoint's recompute.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+#include "lbdev.hpp"
+
+namespace hlb {
+
+// ---------------------------------------------------------------------------
+// fused pull stream + LBGK collide
+// ---------------------------------------------------------------------------
+// Build-time tuning knobs (every variant computes the same result):
+//   HLB_NT_STORE  nontemporal stores of the post-collision populations
+//   HLB_NT_TABLE  nontemporal loads of the neighbour table
+//   HLB_SC_BLOCK  threads per block of this kernel (a multiple of 64)
+#ifndef HLB_NT_STORE
+#define HLB_NT_STORE 1
+#endif
+#ifndef HLB_NT_TABLE
+#define HLB_NT_TABLE 1
+#endif
+#ifndef HLB_SC_BLOCK
+#define HLB_SC_BLOCK 256
+#endif
+constexpr int kScBlock = HLB_SC_BLOCK;
+static_assert(kScBlock == 4 * kTile, "a workgroup covers one group of four tiles");
+
+template <class T>
+__device__ inline void st_pop(T* p, T v) {
+#if HLB_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Incoming population of iolet link l (direction i) of a site whose stored
+// populations decode to vs, at time t (the definition the ghost-fill kernel applies).
+template <int Q>
+__device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const float (&vs)[Q],
+                                    int64_t t) {
+    using Lt = Lat<Q>;
+    const int k = G.iolet[l];
+    const double v = G.vals[(t - G.vals_t0) * G.n_iolets + k];
+    if (G.iolets[k].kind == 0) {
+        float drho, mx, my, mz;
+        moments<Q>(vs, drho, mx, my, mz);
+        const float ir = 1.0f / (1.0f + drho);
+        const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+        const float cu = (float)Lt::cx[i] * ux + (float)Lt::cy[i] * uy + (float)Lt::cz[i] * uz;
+        const float usq = ux * ux + uy * uy + uz * uz;
+        const float rk = (float)v, rk1 = (float)(v - 1.0);
+        return Lt::w[i] * (rk1 + rk * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+    }
+    return vs[opp(i)] + G.coef[l] * (float)v;
+}
+
+// With HLB_FUSE_GHOSTS, a site that owns iolet links also writes the incoming
+// populations of those links for the next step (time t_next) into dst's ghost
+// slots, from its freshly stored populations; the separate ghost fill is then
+// only needed for a state that did not come out of this kernel.
+#ifndef HLB_FUSE_GHOSTS
+#define HLB_FUSE_GHOSTS 1
+#endif
+
+// Pull, collide and store one site whose links are decoded in j.
+template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+__device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
+                                   typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
+                                   const float* __restrict__ alpha, const Ghosts& G,
+                                   int64_t t_next, int32_t s, const int32_t (&j)[Q]) {
+    using C = Codec<Q, ST, SC>;
+    float d[Q];
+    d[0] = C::dec(0, src[tix<Q>(0, s)]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        int dir;
+        int32_t site;
+        link_src(i, j[i], s, dir, site);
+        d[i] = C::dec(i, src[tix<Q>(dir, site)]);
+    }
+    if constexpr (BFL) apply_bfl<Q, ST, SC>(src, s, n, j, d);
+#if HLB_FUSE_GHOSTS
+    // directions of the site's iolet links and the first of those links (they are
+    // consecutive in the link list, in direction order), for the epilogue
+    uint32_t gmask = 0;
+    int64_t gl = -1;
+    {
+        int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
+#pragma unroll
+        for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+        if (top >= n) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i)
+                if (j[i] >= n) {
+                    if (gl < 0) gl = ghost_link<Q>(G, n, j[i], i);
+                    gmask |= 1u << i;
+                }
+        }
+    }
+#endif
+
+    float drho, mx, my, mz;
+    moments<Q>(d, drho, mx, my, mz);
+    const float rho = 1.0f + drho;
+    const float ir = 1.0f / rho;
+    float ux = mx * ir, uy = my * ir, uz = mz * ir;
+    if constexpr (BRINK) {
+        const float a = 1.0f - alpha[s];
+        ux *= a;
+        uy *= a;
+        uz *= a;
+    }
+    float deq[Q];
+    eq_dev<Q>(drho, rho, ux, uy, uz, deq);
+    float vs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const typename Store<ST>::T e = C::enc(i, d[i] - omega * (d[i] - deq[i]));
+        st_pop(dst + tix<Q>(i, s), e);
+        vs[i] = C::dec(i, e);
+    }
+#if HLB_FUSE_GHOSTS
+    // The iolet links of a site are consecutive in the link list, in direction
+    // order.  With one slot per link (table encodings) the first one is the
+    // smallest ghost slot the site pulls from; with shared ghost cells (block
+    // addressing) it is found by a binary search of the list.
+    if (gmask) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (gmask & (1u << i)) {
+                dst[tix<Q>(i, ghost_slot(G, n, gl))] = C::enc(i, ghost_value<Q>(G, gl, i, vs, t_next));
+                ++gl;
+            }
+    }
+#else
+    (void)vs;
+    (void)G;
+    (void)t_next;
+#endif
+}
+
+// Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
+// xcd_group = G > 0, every XCD takes G consecutive blocks of a window of 8G
+// blocks, so neighbouring sites share an L2 while all XCDs still sweep the
+// Morton order together (and share the last-level cache).
+__device__ inline int32_t xcd_block(int32_t b, int32_t xcd_group) {
+    if (xcd_group > 0) {
+        const int32_t w = 8 * xcd_group;
+        b = (b / w) * w + (b & 7) * xcd_group + (b >> 3) % xcd_group;
+    }
+    return b;
+}
+
+// One workgroup (group g of four tiles) of the fused step.  Every thread of the
+// workgroup calls it.
+template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+__device__ inline void stream_collide_group(const typename Store<ST>::T* __restrict__ src,
+                                            typename Store<ST>::T* __restrict__ dst,
+                                            const Table& tb, int32_t n, int32_t g, float omega,
+                                            const float* __restrict__ alpha, const Ghosts& G,
+                                            int64_t t_next, StageLds& lds) {
+    if (g * kScBlock >= n) return;  // the whole workgroup lies past the end
+    const int32_t s = g * kScBlock + (int32_t)threadIdx.x;
+    const bool live = (s & ~(kTile - 1)) < n;  // the wavefront's tile has sites
+    // all link decoding, then all population gathers, before any arithmetic
+    int32_t j[Q];
+    links_group<Q, HLB_NT_TABLE != 0>(tb, g, s, live, lds, j);
+    if (!live || s >= n) return;
+    site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j);
+}
+
+}  // namespace hlb

@@ -350,6 +350,23 @@ class LB:
                                                    int(t0), int(steps)))
         self._keep = checkpoint
 
+    def adjoint_run(self, segments):
+        """The whole reverse sweep: `segments` is a list of (t0, steps, checkpoint)
+        in forward order (checkpoint = raw state [Q, N] at time t0); recomputes
+        overlap the adjoint steps on a second stream (hemelb_lb_adjoint_run)."""
+        keep = []
+        for _, _, ck in segments:
+            ck = ck.contiguous()
+            if ck.dtype != self._raw_dtype() or tuple(ck.shape) != (self.q, self.n):
+                raise ValueError("checkpoint must be a raw state [Q, N]")
+            keep.append(ck)
+        k = len(segments)
+        ptrs = (ctypes.c_void_p * max(k, 1))(*[c.data_ptr() for c in keep])
+        t0 = (ctypes.c_int64 * max(k, 1))(*[int(s[0]) for s in segments])
+        st = (ctypes.c_int64 * max(k, 1))(*[int(s[1]) for s in segments])
+        L.check(self.lib.hemelb_lb_adjoint_run(self.h, ptrs, t0, st, k))
+        self._keep = keep
+
     def theta_sizes(self):
         """Number of Fourier coefficients of each velocity iolet, in id order."""
         return [(k, 1 + 2 * len(getattr(io, "cos", ()))) for k, io in enumerate(self.iolets)

@@ -66,7 +66,7 @@ def _problem(g, T, W, seed=4, amax=0.01, dome_fn=None, q=15, start_amp=0.0):
                 ahat=ahat, g0=g0, T=T, lattice=q, d0=d0)
 
 
-def _gpu_run(P, K, addressing="auto"):
+def _gpu_run(P, K, addressing="auto", pipelined=False):
     g, obj = P["g"], P["obj"]
     lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32),
                           addressing=addressing)
@@ -81,8 +81,11 @@ def _gpu_run(P, K, addressing="auto"):
     J = lb.objective_value()
     q = lb.objective_flux()
     lb.adjoint_begin(K)
-    for t0, k, ck in reversed(cks):
-        lb.adjoint_segment(ck, t0, k)
+    if pipelined:
+        lb.adjoint_run(cks)
+    else:
+        for t0, k, ck in reversed(cks):
+            lb.adjoint_segment(ck, t0, k)
     th, da = lb.adjoint_grads()
     g0 = lb.get_adjoint().cpu().numpy().astype(np.float64)
     return J, q, th[0], da, g0
@@ -119,6 +122,33 @@ def test_segmentation_is_exact(tiny):
     a = _gpu_run(tiny, 40)
     b = _gpu_run(tiny, 7)
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("K", [40, 7, 3])
+def test_pipelined_sweep_is_bit_identical(tiny, K):
+    """hemelb_lb_adjoint_run (recompute of the next segment on a second stream,
+    two tapes) gives the bits of the segment-by-segment sweep."""
+    _gpu()
+    a = _gpu_run(tiny, K)
+    b = _gpu_run(tiny, K, pipelined=True)
+    for x, y in zip(a[2:], b[2:]):
+        assert np.array_equal(x, y)
+
+
+def test_pipelined_sweep_rejects_gaps(tiny):
+    _gpu()
+    from paper_1906_11925_amd import HemelbError
+    g, obj = tiny["g"], tiny["obj"]
+    lb = LB.from_geometry(g, alpha=tiny["alpha"].astype(np.float32))
+    lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+    cks = []
+    for t0 in range(0, 40, 10):
+        cks.append((t0, 10, lb.get_state()[0].clone()))
+        lb.step(10)
+    lb.adjoint_begin(10)
+    with pytest.raises(HemelbError):
+        lb.adjoint_run([cks[0], cks[2], cks[3]])  # a gap between 10 and 20
+    lb.adjoint_run(cks)
 
 
 def test_addressing_modes_give_identical_gradients(tiny):
