@@ -255,14 +255,19 @@ __device__ inline void adj_scatter_group(
     static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
     const int32_t s = grp * kBlock + threadIdx.x;
     const bool live = (s & ~(kTile - 1)) < n;
+    const bool mine = live && s < n;
+    // the incoming adjoints and per-site inputs do not depend on the links: issue
+    // their loads before the link decode so the two latencies overlap
+    float g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = mine ? gin[tix<Q>(i, s)] : 0.f;
+    const float keep = BRINK && mine ? 1.0f - alpha[s] : 1.0f;
+    const float ws = wss_w && mine ? wss_w[s] : 0.f;
     float d[Q];
     int32_t j[Q];
     links_group<Q, false>(tb, grp, s, live, lds, j);
-    if (!live || s >= n) return;
+    if (!mine) return;
     gather_pre<Q, ST, SC>(A, s, n, d, j);
-    float g[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = gin[tix<Q>(i, s)];
     // a site with iolet links: find its entry and add what the later step left pending
     int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
 #pragma unroll
@@ -283,7 +288,6 @@ __device__ inline void adj_scatter_group(
     const float rho = 1.0f + drho;
     const float ir = 1.0f / rho;
     const float ux = mx * ir, uy = my * ir, uz = mz * ir;
-    const float keep = BRINK ? 1.0f - alpha[s] : 1.0f;
     const float bx = keep * ux, by = keep * uy, bz = keep * uz;
     const float ub2 = bx * bx + by * by + bz * bz;
     const float ubu = bx * ux + by * uy + bz * uz;
@@ -315,7 +319,6 @@ __device__ inline void adj_scatter_group(
 
     // wall-shear objective: dWSS/df_j = -(1 - omega/2) (t^.(c_j - u)) (n.(c_j - u))
     if (wss_w) {
-        const float ws = wss_w[s];
         if (ws != 0.f) {
             const float nx = normal[s], ny = normal[n + s], nz = normal[2 * (int64_t)n + s];
             float tx, ty, tz;
@@ -361,24 +364,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(
                                         G, I, (int32_t)blockIdx.x, lds);
 }
 
-// A recompute step of one segment (blocks below nb_fwd) and a reverse step of
-// the next later segment (the other blocks) in one launch: the two touch disjoint
+// A reverse step of one segment (blocks below nb) and a recompute step of the
+// next earlier segment (the other blocks) in one launch: the two touch disjoint
 // buffers, and for a lattice too small to fill the GPU each half runs beside the
-// other instead of after it.
+// other instead of after it.  The longer reverse half is dispatched first, so the
+// recompute workgroups fill the compute units as they drain.
 template <int Q, int ST, bool SC, bool BRINK>
 __global__ __launch_bounds__(kBlock) void k_adj_dual(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    Ghosts Gf, int64_t t_next, int32_t nb_fwd, const typename Store<ST>::T* __restrict__ A,
+    Ghosts Gf, int64_t t_next, int32_t nb, const typename Store<ST>::T* __restrict__ A,
     const float* __restrict__ gin, float* __restrict__ gout, Table tb, int32_t n, float omega,
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
     __shared__ StageLds lds;
-    if ((int32_t)blockIdx.x < nb_fwd)
-        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, (int32_t)blockIdx.x, omega,
-                                                      alpha, Gf, t_next, lds);
-    else
+    if ((int32_t)blockIdx.x < nb)
         adj_scatter_group<Q, ST, SC, BRINK>(A, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
-                                            normal, G, I, (int32_t)blockIdx.x - nb_fwd, lds);
+                                            normal, G, I, (int32_t)blockIdx.x, lds);
+    else
+        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, (int32_t)blockIdx.x - nb,
+                                                      omega, alpha, Gf, t_next, lds);
 }
 
 // adds what the last reverse step left pending to the sites' own populations

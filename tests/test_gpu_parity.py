@@ -140,7 +140,6 @@ def test_one_step_f32_elementwise(name, q):
     assert np.abs(w - ow).max() < tol
 
 
-@pytest.mark.parametrize("storage", ["f16", "bf16"])
 def _tol16(o, ref, f, storage, q):
     """Bound on one 16-bit step (see test_one_step_16bit_elementwise): the output
     rounding, FP32 collision error, and the rounding of the incoming iolet values
@@ -155,6 +154,7 @@ def _tol16(o, ref, f, storage, q):
     return plain_tol + 3.0 * g_err[None, :], plain_tol, ~ghost.any(axis=0)
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_one_step_16bit_elementwise(storage):
     """16-bit storage: the input is exact, one FP32 collision follows, then one
     rounding of d * scale (relative half-ulp 2^-11 for FP16, 2^-8 for BF16).
