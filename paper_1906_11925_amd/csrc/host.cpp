@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,6 +108,23 @@ inline uint64_t morton(int32_t x, int32_t y, int32_t z) {
     return spread3((uint64_t)x) | (spread3((uint64_t)y) << 1) | (spread3((uint64_t)z) << 2);
 }
 
+// Setup progress on stderr, one line per phase, when HEMELB_VERBOSE is set in the
+// environment (planning a lattice of several hundred million sites takes minutes).
+struct Progress {
+    using clock = std::chrono::steady_clock;
+    bool on = std::getenv("HEMELB_VERBOSE") != nullptr;
+    clock::time_point t0 = clock::now(), last = t0;
+    void operator()(const char* phase) {
+        if (!on) return;
+        const clock::time_point t = clock::now();
+        std::fprintf(stderr, "[hemelb] %-30s %7.2f s  (%.1f s in all)\n", phase,
+                     std::chrono::duration<double>(t - last).count(),
+                     std::chrono::duration<double>(t - t0).count());
+        std::fflush(stderr);
+        last = t;
+    }
+};
+
 template <class F>
 void parallel_for(int64_t n, F&& f) {
     unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -120,6 +139,35 @@ void parallel_for(int64_t n, F&& f) {
         th.emplace_back([=, &f] { f(a, b); });
     }
     for (auto& x : th) x.join();
+}
+
+// Sort v by `less`: chunks sorted in parallel, then merged pairwise in parallel.
+template <class T, class Less>
+void parallel_sort(std::vector<T>& v, Less less) {
+    const int64_t n = (int64_t)v.size();
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 1000000 || nt == 1) {
+        std::sort(v.begin(), v.end(), less);
+        return;
+    }
+    std::vector<int64_t> cut(nt + 1);
+    for (unsigned t = 0; t <= nt; ++t) cut[t] = n * t / nt;
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], less); });
+        for (auto& x : th) x.join();
+    }
+    for (size_t w = 1; w < nt; w *= 2) {
+        std::vector<std::thread> th;
+        for (size_t a = 0; a + w < nt; a += 2 * w) {
+            const int64_t lo = cut[a], mid = cut[a + w], hi = cut[std::min<size_t>(a + 2 * w, nt)];
+            th.emplace_back([&, lo, mid, hi] {
+                std::inplace_merge(v.begin() + lo, v.begin() + mid, v.begin() + hi, less);
+            });
+        }
+        for (auto& x : th) x.join();
+    }
 }
 
 }  // namespace
@@ -351,7 +399,23 @@ int validate(const hemelb_lb_desc_t* d) {
     if (n == 0) return HEMELB_OK;
     if (!d->nbr) return fail(HEMELB_EINVAL, "nbr is NULL");
     const int32_t* nb = d->nbr;
-    for (int64_t s = 0; s < n; ++s)
+    // find the first site with a bad link in parallel; the loop below then names it
+    std::atomic<int64_t> first{n};
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b && s < first.load(std::memory_order_relaxed); ++s)
+            for (int i = 1; i < q; ++i) {
+                const int32_t v = nb[s * q + i];
+                const bool bad = v >= 0 ? (v >= n || nb[(int64_t)v * q + opp_dir(i)] != s)
+                                        : (v != HEMELB_LINK_WALL && (-2 - v < 0 || -2 - v >= d->n_iolets));
+                if (bad) {
+                    int64_t cur = first.load();
+                    while (s < cur && !first.compare_exchange_weak(cur, s)) {
+                    }
+                    return;
+                }
+            }
+    });
+    for (int64_t s = first.load(); s < n; ++s)
         for (int i = 1; i < q; ++i) {
             const int32_t v = nb[s * q + i];
             if (v >= 0) {
@@ -768,9 +832,10 @@ struct HostPlan {
 };
 
 // Validate d and build the host side of its layout (no device work).
-int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
+int make_plan(const hemelb_lb_desc_t* d, HostPlan& P, Progress& prog) {
     int rc = validate(d);
     if (rc) return rc;
+    prog("validate");
     const int q = d->lattice;
     const int64_t n = d->n_sites;
     P.n = n;
@@ -792,7 +857,7 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
                 ki[s] = KI{morton(c[0], c[1], c[2]), (int32_t)s};
             }
         });
-        std::sort(ki.begin(), ki.end(), [](const KI& a, const KI& b) {
+        parallel_sort(ki, [](const KI& a, const KI& b) {
             return a.key < b.key || (a.key == b.key && a.idx < b.idx);
         });
         for (int64_t m = 0; m < n; ++m) P.order[m] = ki[m].idx;
@@ -802,6 +867,7 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
                             ki[m - 1].idx, ki[m].idx);
     }
     for (int64_t m = 0; m < n; ++m) P.inv[P.order[m]] = (int32_t)m;
+    prog("site order");
 
     // iolet links in Morton site order, direction ascending
     for (int64_t m = 0; m < n; ++m) {
@@ -832,6 +898,7 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
     std::vector<int64_t> gbase(n + 1, 0);  // first iolet link of each Morton site
     for (int64_t l = 0; l < P.nghost; ++l) gbase[P.gsite[l] + 1]++;
     for (int64_t m = 0; m < n; ++m) gbase[m + 1] += gbase[m];
+    prog("iolet links");
 
     // addressing: asked for, or by default block addressing for 16-bit storage (where
     // it applies) and the explicit table otherwise -- the faster form of each on
@@ -850,6 +917,7 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
             blocks = build_blocks(d, lat, P.order, P.inv, gbase, P.gsite, P.gdir, P.giol, P.ttiles,
                                   P.bp);
     }
+    if (try_blocks && n > 0) prog("block addressing");
     if ((d->flags & HEMELB_FLAG_BLOCKS) && n > 0 && !blocks)
         return fail(HEMELB_EINVAL, "block addressing does not apply: %s", P.bp.why.c_str());
     const int64_t ghost_slots = blocks ? P.bp.ncells : P.nghost;
@@ -864,59 +932,89 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
         // interpolated-wall fraction in units of 2^-15 in the low bits (0: halfway);
         // iolet -> ghost slot n + l
         std::vector<int32_t> tbl((size_t)P.ttiles * (q - 1) * hlb::kTile, 0);
-        for (int64_t m = 0; m < n; ++m) {
-            const int64_t s = P.order[m];
-            int64_t g = gbase[m];
-            for (int i = 1; i < q; ++i) {
-                const int32_t v = d->nbr[s * q + i];
-                uint32_t e;
-                if (v >= 0)
-                    e = (uint32_t)P.inv[v];
-                else if (v == HEMELB_LINK_WALL)
-                    e = 0x80000000u | (d->wall_q ? wall_code(d->wall_q[s * q + i]) : 0u);
-                else
-                    e = (uint32_t)(n + (g++));
-                const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
-                                  (size_t)(m % hlb::kTile);
-                tbl[at] = (int32_t)e;
+        parallel_for(n, [&](int64_t a, int64_t b) {
+            for (int64_t m = a; m < b; ++m) {
+                const int64_t s = P.order[m];
+                int64_t g = gbase[m];
+                for (int i = 1; i < q; ++i) {
+                    const int32_t v = d->nbr[s * q + i];
+                    uint32_t e;
+                    if (v >= 0)
+                        e = (uint32_t)P.inv[v];
+                    else if (v == HEMELB_LINK_WALL)
+                        e = 0x80000000u | (d->wall_q ? wall_code(d->wall_q[s * q + i]) : 0u);
+                    else
+                        e = (uint32_t)(n + (g++));
+                    const size_t at = ((size_t)(m / hlb::kTile) * (q - 1) + (i - 1)) * hlb::kTile +
+                                      (size_t)(m % hlb::kTile);
+                    tbl[at] = (int32_t)e;
+                }
             }
-        }
-        // compact form: 16-bit codes against a per-tile list of source tiles
+        });
+        prog("neighbour table");
+        // compact form: 16-bit codes against a per-tile list of source tiles.  Tiles
+        // are independent: codes and list lengths first, then the lists at their offsets.
         bool compact = !(d->flags & HEMELB_FLAG_TABLE32);
         if (compact) {
-            P.t16.assign(tbl.size(), 0);
-            P.toff.assign((size_t)P.ttiles + 1, 0);
-            std::vector<int32_t> tiles;
-            for (int64_t T = 0; T < P.ttiles && compact; ++T) {
+            const size_t per = (size_t)(q - 1) * hlb::kTile;
+            // sorted distinct source tiles of tile T
+            auto sources = [&](int64_t T, std::vector<int32_t>& tiles) {
                 tiles.clear();
-                const size_t base = (size_t)T * (q - 1) * hlb::kTile;
-                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
+                const size_t base = (size_t)T * per;
+                for (size_t e = 0; e < per; ++e) {
                     const int32_t v = tbl[base + e];
                     if (v >= 0) tiles.push_back(v >> hlb::kTileShift);
                 }
                 std::sort(tiles.begin(), tiles.end());
                 tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
-                if (tiles.size() > 2 * (size_t)hlb::kTile) {
-                    compact = false;
-                    break;
-                }
-                P.toff[T] = (int32_t)P.tlist.size();
-                for (size_t e = 0; e < (size_t)(q - 1) * hlb::kTile; ++e) {
-                    const int32_t v = tbl[base + e];
-                    uint16_t c;
-                    if (v < 0) {
-                        c = (uint16_t)(0x8000u | ((uint32_t)v & 0x7fffu));
-                    } else {
-                        const int32_t slot = (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
-                                                                        v >> hlb::kTileShift) -
-                                                       tiles.begin());
-                        c = (uint16_t)((slot << hlb::kTileShift) | (v & (hlb::kTile - 1)));
+            };
+            P.t16.assign(tbl.size(), 0);
+            std::vector<int64_t> count((size_t)P.ttiles, 0);
+            std::atomic<bool> fits{true};
+            parallel_for(P.ttiles, [&](int64_t a, int64_t b) {
+                std::vector<int32_t> tiles;
+                for (int64_t T = a; T < b && fits.load(std::memory_order_relaxed); ++T) {
+                    sources(T, tiles);
+                    if (tiles.size() > 2 * (size_t)hlb::kTile) {
+                        fits = false;
+                        break;
                     }
-                    P.t16[base + e] = c;
+                    count[T] = (int64_t)tiles.size();
+                    const size_t base = (size_t)T * per;
+                    for (size_t e = 0; e < per; ++e) {
+                        const int32_t v = tbl[base + e];
+                        uint16_t c;
+                        if (v < 0) {
+                            c = (uint16_t)(0x8000u | ((uint32_t)v & 0x7fffu));
+                        } else {
+                            const int32_t slot =
+                                (int32_t)(std::lower_bound(tiles.begin(), tiles.end(),
+                                                           v >> hlb::kTileShift) -
+                                          tiles.begin());
+                            c = (uint16_t)((slot << hlb::kTileShift) | (v & (hlb::kTile - 1)));
+                        }
+                        P.t16[base + e] = c;
+                    }
                 }
-                P.tlist.insert(P.tlist.end(), tiles.begin(), tiles.end());
+            });
+            compact = fits.load();
+            if (compact) {
+                P.toff.assign((size_t)P.ttiles + 1, 0);
+                int64_t total = 0;
+                for (int64_t T = 0; T < P.ttiles; ++T) {
+                    P.toff[T] = (int32_t)total;
+                    total += count[T];
+                }
+                P.toff[P.ttiles] = (int32_t)total;
+                P.tlist.assign((size_t)total, 0);
+                parallel_for(P.ttiles, [&](int64_t a, int64_t b) {
+                    std::vector<int32_t> tiles;
+                    for (int64_t T = a; T < b; ++T) {
+                        sources(T, tiles);
+                        std::copy(tiles.begin(), tiles.end(), P.tlist.begin() + P.toff[T]);
+                    }
+                });
             }
-            P.toff[P.ttiles] = (int32_t)P.tlist.size();
         }
         if (compact) {
             if (P.tlist.empty()) P.tlist.push_back(0);
@@ -929,24 +1027,27 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
             P.tbl = std::move(tbl);
             P.addr_bytes = 4.0 * (q - 1) * (double)n;
         }
+        prog("compact table");
     }
 
     // wall normals [3][n] in Morton order
     P.nrm.assign((size_t)3 * n, 0.f);
-    for (int64_t m = 0; m < n; ++m) {
-        const int64_t s = P.order[m];
-        double v[3] = {0, 0, 0};
-        if (d->wall_normal) {
-            for (int a = 0; a < 3; ++a) v[a] = d->wall_normal[3 * s + a];
-        } else {
-            for (int i = 1; i < q; ++i)
-                if (d->nbr[s * q + i] == HEMELB_LINK_WALL)
-                    for (int a = 0; a < 3; ++a) v[a] += lat.c[i][a];
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t m = lo; m < hi; ++m) {
+            const int64_t s = P.order[m];
+            double v[3] = {0, 0, 0};
+            if (d->wall_normal) {
+                for (int a = 0; a < 3; ++a) v[a] = d->wall_normal[3 * s + a];
+            } else {
+                for (int i = 1; i < q; ++i)
+                    if (d->nbr[s * q + i] == HEMELB_LINK_WALL)
+                        for (int a = 0; a < 3; ++a) v[a] += lat.c[i][a];
+            }
+            const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (nn > 0)
+                for (int a = 0; a < 3; ++a) P.nrm[(size_t)a * n + m] = (float)(v[a] / nn);
         }
-        const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (nn > 0)
-            for (int a = 0; a < 3; ++a) P.nrm[(size_t)a * n + m] = (float)(v[a] / nn);
-    }
+    });
 
     // iolet descriptors and harmonics
     P.dio.resize(d->n_iolets);
@@ -966,6 +1067,7 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P) {
         P.alpha.resize(n);
         for (int64_t m = 0; m < n; ++m) P.alpha[m] = d->alpha[P.order[m]];
     }
+    prog("normals and site data");
     return HEMELB_OK;
 }
 
@@ -1265,7 +1367,8 @@ int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t
 int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
     if (!info) return fail(HEMELB_EINVAL, "info is NULL");
     HostPlan P;
-    int rc = make_plan(d, P);
+    Progress prog;
+    int rc = make_plan(d, P, prog);
     if (rc) return rc;
     const size_t elem = d->storage == HEMELB_STORE_F32 ? 4 : 2;
     info->n_sites = P.n;
@@ -1285,7 +1388,8 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     if (!out) return fail(HEMELB_EINVAL, "out is NULL");
     *out = nullptr;
     HostPlan P;
-    int rc = make_plan(d, P);
+    Progress prog;
+    int rc = make_plan(d, P, prog);
     if (rc) return rc;
     hemelb_lb* h = new (std::nothrow) hemelb_lb();
     if (!h) return fail(HEMELB_ENOMEM, "handle allocation failed");
@@ -1399,6 +1503,7 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
         return hip_fail(e, "create sync");
     }
 #undef TRY
+    prog("device upload");
     h->order = std::move(P.order);
     h->h_gsite = std::move(P.gsite);
     h->h_gdir = std::move(P.gdir);
