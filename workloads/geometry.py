@@ -436,7 +436,14 @@ def periodic_box(X=6, Y=5, Z=7, tau=0.7):
 def config_geometry(name: str) -> Geometry:
     """The named workloads: pipe (13,312 sites), aneurysm (~1.6M), tree1024
     (Murray tree, root radius 32, 7 generations, seed 3), aneurysm_half (~200k),
-    tree2048 (root radius 64, 8 generations, seed 5)."""
+    tree2048 (root radius 64, 8 generations, seed 5).
+
+    Size-matched variants of the two trees keep the box, seed and branching rules
+    and raise only the root radius until the site count reaches the stated ~30M and
+    ~400M (branches clipped at the box faces make the count grow more slowly than
+    r^3): tree1024_30M (radius 96, 30,090,542 sites) and tree2048_400M (radius 256,
+    395,245,440 sites).  As in the originals the root starts half a radius above
+    the bottom face."""
     if name == "pipe":
         return pipe()
     if name == "aneurysm":
@@ -447,4 +454,8 @@ def config_geometry(name: str) -> Geometry:
         return tree(1024, 32.0, (512.0, 512.0, 16.0), 7, seed=3, name="tree1024")
     if name == "tree2048":
         return tree(2048, 64.0, (1024.0, 1024.0, 32.0), 8, seed=5, name="tree2048")
+    if name == "tree1024_30M":
+        return tree(1024, 96.0, (512.0, 512.0, 48.0), 7, seed=3, name="tree1024_30M")
+    if name == "tree2048_400M":
+        return tree(2048, 256.0, (1024.0, 1024.0, 128.0), 8, seed=5, name="tree2048_400M")
     raise ValueError(f"unknown workload {name!r}")
