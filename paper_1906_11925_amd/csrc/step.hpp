@@ -17,18 +17,16 @@ namespace hlb {
 // Build-time tuning knobs (every variant computes the same result):
 //   HLB_NT_STORE  nontemporal stores of the post-collision populations
 //   HLB_NT_TABLE  nontemporal loads of the neighbour table
-//   HLB_SC_BLOCK  threads per block of this kernel (a multiple of 64)
 #ifndef HLB_NT_STORE
 #define HLB_NT_STORE 1
 #endif
 #ifndef HLB_NT_TABLE
 #define HLB_NT_TABLE 1
 #endif
-#ifndef HLB_SC_BLOCK
-#define HLB_SC_BLOCK 256
-#endif
-constexpr int kScBlock = HLB_SC_BLOCK;
-static_assert(kScBlock == 4 * kTile, "a workgroup covers one group of four tiles");
+// One workgroup covers one group of four tiles (the unit of the staged block
+// records).  Groups of 8 or 16 tiles per workgroup (more neighbours sharing one
+// L1) measured no faster with the explicit tables.
+constexpr int kScBlock = 4 * kTile;
 
 template <class T>
 __device__ inline void st_pop(T* p, T v) {
