@@ -68,6 +68,33 @@ def timed_run(lb, steps, warmup, obs_every=0, events=None):
     return time.perf_counter() - t0
 
 
+def aux_timings(lb, n, q, elem, bpu, reps=20):
+    """The on-demand outputs on the benchmark's lattice: one observables pass
+    (HIP events around `reps` calls; it re-gathers the last step's pre-collision
+    populations and writes p, u, WSS in caller order) and one FP64 totals call
+    (host wall time, including its synchronisation and the copy of 4 doubles)."""
+    import torch
+    obs = lb.observables()
+    lb.totals()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lb.observables_into(*obs)
+    e1.record()
+    torch.cuda.synchronize()
+    obs_ms = e0.elapsed_time(e1) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lb.totals()
+    tot_ms = (time.perf_counter() - t0) / reps * 1e3
+    obs_bytes = bpu - q * elem + 20.0  # one step's reads (populations + addressing) + 20 B out
+    return {"observables_ms": obs_ms,
+            "observables_GBs_algorithmic": obs_bytes * n / (obs_ms * 1e-3) / 1e9,
+            "totals_ms_incl_sync": tot_ms,
+            "totals_GBs_algorithmic": q * elem * n / (tot_ms * 1e-3) / 1e9}
+
+
 def region_kernel_ms(lb, steps, warmup):
     """Average duration of the fused stream+collide kernel: HIP events on the
     library's stream around `steps` back-to-back steps, each of which is one
@@ -300,6 +327,9 @@ def main():
     log(f"[bench] {glups:.2f} GLUPS, {ms_step:.4f} ms/step, kernel {avg_ms:.4f} ms "
         f"-> {achieved:.0f} GB/s algorithmic")
     render = None if args.no_extra else render_run(lb, geom)
+    elem = 4 if args.storage == "f32" else 2
+    aux = aux_timings(lb, n, args.lattice, elem, info["bytes_per_update"])
+    log(f"[bench] observables {aux['observables_ms']:.3f} ms, totals {aux['totals_ms_incl_sync']:.3f} ms")
     lb.close()
 
     pop_bytes = 2 * args.lattice * (4 if args.storage == "f32" else 2)
@@ -321,6 +351,7 @@ def main():
         copy_probe(b, a, nbytes)
     torch.cuda.synchronize()
     copy_gbs = 2 * nbytes * reps / (time.perf_counter() - t0) / 1e9
+    extra["outputs"] = aux
     if render:
         extra["render"] = render
     extra["copy_GBs"] = copy_gbs
