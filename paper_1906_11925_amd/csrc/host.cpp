@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <numeric>
 #include <string>
@@ -125,48 +126,77 @@ struct Progress {
     }
 };
 
+unsigned worker_count() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+
+// Run task(0) .. task(count - 1), each on its own thread except task 0, which
+// runs on the caller's.  A task that cannot get a thread runs on the caller's
+// thread too.  Every thread is joined before the first exception a task threw is
+// rethrown, so no exception leaves a thread or a joinable std::thread behind.
+template <class Task>
+void run_tasks(unsigned count, Task&& task) {
+    std::vector<std::exception_ptr> err(count);
+    auto run = [&](unsigned k) {
+        try {
+            task(k);
+        } catch (...) {
+            err[k] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned k = 1; k < count; ++k) {
+        bool started = false;
+        try {
+            th.emplace_back(run, k);
+            started = true;
+        } catch (...) {
+        }
+        if (!started) run(k);
+    }
+    if (count > 0) run(0);
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+// f(a, b) over contiguous chunks [a, b) of [0, n), in parallel for large n
 template <class F>
 void parallel_for(int64_t n, F&& f) {
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 100000) nt = 1;
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nt; ++t) {
-        const int64_t a = n * t / nt, b = n * (t + 1) / nt;
-        if (nt == 1) {
-            f(a, b);
-            return;
-        }
-        th.emplace_back([=, &f] { f(a, b); });
-    }
-    for (auto& x : th) x.join();
+    const unsigned nt = n < 100000 ? 1u : worker_count();
+    run_tasks(nt, [&](unsigned t) { f(n * t / nt, n * (t + 1) / nt); });
 }
 
 // Sort v by `less`: chunks sorted in parallel, then merged pairwise in parallel.
 template <class T, class Less>
 void parallel_sort(std::vector<T>& v, Less less) {
     const int64_t n = (int64_t)v.size();
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nt = worker_count();
     if (n < 1000000 || nt == 1) {
         std::sort(v.begin(), v.end(), less);
         return;
     }
     std::vector<int64_t> cut(nt + 1);
     for (unsigned t = 0; t <= nt; ++t) cut[t] = n * t / nt;
-    {
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nt; ++t)
-            th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], less); });
-        for (auto& x : th) x.join();
-    }
+    run_tasks(nt, [&](unsigned t) { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], less); });
     for (size_t w = 1; w < nt; w *= 2) {
-        std::vector<std::thread> th;
-        for (size_t a = 0; a + w < nt; a += 2 * w) {
+        const unsigned pairs = (unsigned)((nt - w + 2 * w - 1) / (2 * w));  // a = 0, 2w, .. with a + w < nt
+        run_tasks(pairs, [&](unsigned k) {
+            const size_t a = 2 * w * k;
             const int64_t lo = cut[a], mid = cut[a + w], hi = cut[std::min<size_t>(a + 2 * w, nt)];
-            th.emplace_back([&, lo, mid, hi] {
-                std::inplace_merge(v.begin() + lo, v.begin() + mid, v.begin() + hi, less);
-            });
-        }
-        for (auto& x : th) x.join();
+            std::inplace_merge(v.begin() + lo, v.begin() + mid, v.begin() + hi, less);
+        });
+    }
+}
+
+// Host-side C++ exceptions (an allocation or a thread start failing) become error
+// codes: none may cross the C ABI.
+template <class F>
+int no_throw(F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(HEMELB_ENOMEM, "host memory allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HEMELB_EDEVICE, "host error: %s", e.what());
     }
 }
 
@@ -1268,7 +1298,7 @@ const char* hemelb_lb_strerror(int code) {
     }
 }
 
-int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t periodic[3],
+static int links_impl(const uint8_t* labels, const int32_t shape[3], const int32_t periodic[3],
                     int32_t lattice, int64_t* n_sites, int32_t* coords, int32_t* nbr) {
     if (!labels || !shape || !n_sites) return fail(HEMELB_EINVAL, "NULL argument");
     if (lattice != 15 && lattice != 19) return fail(HEMELB_EINVAL, "lattice must be 15 or 19");
@@ -1364,7 +1394,12 @@ int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t
     return HEMELB_OK;
 }
 
-int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
+int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t periodic[3],
+                    int32_t lattice, int64_t* n_sites, int32_t* coords, int32_t* nbr) {
+    return no_throw([&] { return links_impl(labels, shape, periodic, lattice, n_sites, coords, nbr); });
+}
+
+static int plan_impl(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
     if (!info) return fail(HEMELB_EINVAL, "info is NULL");
     HostPlan P;
     Progress prog;
@@ -1384,15 +1419,14 @@ int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
-    if (!out) return fail(HEMELB_EINVAL, "out is NULL");
-    *out = nullptr;
-    HostPlan P;
-    Progress prog;
-    int rc = make_plan(d, P, prog);
-    if (rc) return rc;
-    hemelb_lb* h = new (std::nothrow) hemelb_lb();
-    if (!h) return fail(HEMELB_ENOMEM, "handle allocation failed");
+int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
+    return no_throw([&] { return plan_impl(d, info); });
+}
+
+// Fill a new handle from plan P: everything of hemelb_lb_create after the handle
+// exists.  On failure h has been released.
+static int init_handle(hemelb_lb* h, hemelb_lb_t* out, const hemelb_lb_desc_t* d, HostPlan& P,
+                       Progress& prog) {
     h->q = d->lattice;
     h->storage = d->storage;
     h->flags = d->flags;
@@ -1510,6 +1544,27 @@ int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
     h->h_giol = std::move(P.giol);
     *out = h;
     return HEMELB_OK;
+}
+
+static int create_impl(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
+    if (!out) return fail(HEMELB_EINVAL, "out is NULL");
+    *out = nullptr;
+    HostPlan P;
+    Progress prog;
+    int rc = make_plan(d, P, prog);
+    if (rc) return rc;
+    hemelb_lb* h = new (std::nothrow) hemelb_lb();
+    if (!h) return fail(HEMELB_ENOMEM, "handle allocation failed");
+    try {
+        return init_handle(h, out, d, P, prog);
+    } catch (...) {
+        release(h);  // a host allocation failed part way: no handle escapes
+        throw;
+    }
+}
+
+int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
+    return no_throw([&] { return create_impl(out, d); });
 }
 
 int hemelb_lb_destroy(hemelb_lb_t h) {
@@ -1657,7 +1712,7 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
+static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
     if (!h || !view || !image || !view->lut || (!values && h->n > 0))
         return fail(HEMELB_EINVAL, "NULL argument");
     if (h->n > 0 && h->h_coords.empty())
@@ -1698,6 +1753,10 @@ int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* vi
     return HEMELB_OK;
 }
 
+int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
+    return no_throw([&] { return render_impl(h, values, view, image); });
+}
+
 int hemelb_copy_probe(void* dst, const void* src, int64_t bytes, void* stream) {
     if (!dst || !src || bytes <= 0 || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return fail(HEMELB_EINVAL, "copy probe needs 16-byte aligned pointers and size");
@@ -1705,7 +1764,7 @@ int hemelb_copy_probe(void* dst, const void* src, int64_t bytes, void* stream) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
+static int set_iolet_impl(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
     if (!h || !io) return fail(HEMELB_EINVAL, "NULL argument");
     if (k < 0 || k >= (int32_t)h->h_iolets.size()) return fail(HEMELB_EINVAL, "no iolet %d", k);
     hemelb_lb::HostIolet& hi = h->h_iolets[k];
@@ -1735,7 +1794,11 @@ int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha) {
+int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
+    return no_throw([&] { return set_iolet_impl(h, k, io); });
+}
+
+static int set_alpha_impl(hemelb_lb_t h, const float* alpha) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     if (!alpha) {
@@ -1761,7 +1824,11 @@ int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
+int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha) {
+    return no_throw([&] { return set_alpha_impl(h, alpha); });
+}
+
+static int set_objective_impl(hemelb_lb_t h, const hemelb_objective_t* obj) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     for (void** p : {(void**)&h->d_out_links, (void**)&h->d_dome, (void**)&h->d_wss_w,
@@ -1818,6 +1885,10 @@ int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
     return HEMELB_OK;
 }
 
+int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
+    return no_throw([&] { return set_objective_impl(h, obj); });
+}
+
 int hemelb_lb_objective_value(hemelb_lb_t h, double* J, double* flux_term, double* wss_term) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (!h->obj_set) return fail(HEMELB_EORDER, "no objective set");
@@ -1852,7 +1923,7 @@ int hemelb_lb_objective_flux(hemelb_lb_t h, double* q) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
+static int adjoint_begin_impl(hemelb_lb_t h, int64_t max_segment) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (!h->obj_set) return fail(HEMELB_EORDER, "set an objective and run the forward first");
     if (h->bfl)
@@ -1912,7 +1983,11 @@ int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps) {
+int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
+    return no_throw([&] { return adjoint_begin_impl(h, max_segment); });
+}
+
+static int adjoint_segment_impl(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (h->adj_t < 0) return fail(HEMELB_EORDER, "call hemelb_lb_adjoint_begin first");
     if (steps < 1 || steps + 1 > (int64_t)h->tape.size())
@@ -1934,7 +2009,11 @@ int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0,
     return HEMELB_OK;
 }
 
-int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
+int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps) {
+    return no_throw([&] { return adjoint_segment_impl(h, checkpoint, t0, steps); });
+}
+
+static int adjoint_run_impl(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
                           const int64_t* steps, int64_t nseg) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (h->adj_t < 0) return fail(HEMELB_EORDER, "call hemelb_lb_adjoint_begin first");
@@ -1997,7 +2076,12 @@ int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const i
     return HEMELB_OK;
 }
 
-int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha) {
+int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
+                          const int64_t* steps, int64_t nseg) {
+    return no_throw([&] { return adjoint_run_impl(h, checkpoints, t0, steps, nseg); });
+}
+
+static int adjoint_grads_impl(hemelb_lb_t h, double* dtheta, double* dalpha) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (h->adj_t < 0) return fail(HEMELB_EORDER, "no adjoint run");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
@@ -2029,7 +2113,11 @@ int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha) {
     return HEMELB_OK;
 }
 
-int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst) {
+int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha) {
+    return no_throw([&] { return adjoint_grads_impl(h, dtheta, dalpha); });
+}
+
+static int get_adjoint_impl(hemelb_lb_t h, float* dst) {
     if (!h || (!dst && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (h->adj_t < 0) return fail(HEMELB_EORDER, "no adjoint run");
     hlb::Layout Lg = h->layout();
@@ -2037,6 +2125,10 @@ int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst) {
     Lg.scaled = false;
     HIP_TRY(hlb::launch_state(Lg, h->ghat[h->gcur], dst, h->perm, 0, h->stream), "adjoint get");
     return HEMELB_OK;
+}
+
+int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst) {
+    return no_throw([&] { return get_adjoint_impl(h, dst); });
 }
 
 }  // extern "C"

@@ -9,6 +9,10 @@ site coordinates and compare.
 """
 
 import math
+import os
+import subprocess
+import sys
+import textwrap
 
 import numpy as np
 import pytest
@@ -17,6 +21,8 @@ import workloads as wl
 from paper_1906_11925_amd import lib as L
 from paper_1906_11925_amd import links, plan
 from paper_1906_11925_amd.lb import lattice_vectors
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _args(g, q=15):
@@ -155,3 +161,31 @@ def test_empty_lattice_plans():
     nbr = np.zeros((0, 15), dtype=np.int32)
     p = plan(nbr, 0.8, coords=np.zeros((0, 3), dtype=np.int32), addressing="blocks")
     assert p["n_sites"] == 0 and p["pitch"] == 64
+
+
+def test_host_allocation_failure_is_an_error_code():
+    """A host allocation that fails inside the planner comes back as
+    HEMELB_ENOMEM (no C++ exception crosses the C ABI, no thread is left
+    running): a child process caps its own address space just above what it
+    holds, then plans a 4M-site periodic box whose tables need far more."""
+    code = textwrap.dedent(f"""
+        import resource, sys
+        sys.path.insert(0, {ROOT!r})
+        import numpy as np
+        import workloads as wl
+        from paper_1906_11925_amd import links, plan, HemelbError
+        from paper_1906_11925_amd import lib as L
+        g = wl.periodic_box(160, 160, 160)
+        coords, nbr = links(g.labels, g.shape, g.periodic, 15)
+        used = int(open("/proc/self/statm").read().split()[0]) * resource.getpagesize()
+        resource.setrlimit(resource.RLIMIT_AS, (used + (96 << 20), resource.RLIM_INFINITY))
+        try:
+            plan(nbr, g.tau, coords=coords)
+        except HemelbError as e:
+            print("code", e.code, str(e))
+            sys.exit(0 if e.code == L.HEMELB_ENOMEM else 3)
+        sys.exit(4)
+    """)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert "allocation" in r.stdout
