@@ -265,7 +265,7 @@ def main():
     ap.add_argument("--workload", default="tree1024")
     ap.add_argument("--lattice", type=int, default=15)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for cpu_baseline (0: skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and adjoint runs")
     ap.add_argument("--obs-every", type=int, default=0,
                     help="also compute velocity/pressure/WSS every k steps inside the timed run")
