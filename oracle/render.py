@@ -13,7 +13,17 @@ formulas; this is the textbook emission-absorption ray marcher (front-to-back
 * Rays: fixed-point integer vectors, F = 2^20 units per lattice spacing.  Ray
   (i, j) starts at P0 = O + i R + j U; its samples are P_k = P0 + k D for
   k = 0 .. K - 1.
-* Sampling: nearest voxel, x = floor((P_k + F/2) / F) on each axis.
+* Sampling, nearest voxel: x = floor((P_k + F/2) / F) on each axis.
+* Sampling, trilinear (the filtering of a 3D texture): base voxel b = floor(P_k / F)
+  and 8-bit fraction a = floor((P_k - b F) / 2^12) in [0, 255] on each axis (the
+  weight precision of texture filtering units).  Corner c in {0, 1}^3 has weight
+  W_c = prod over axes of (a if c = 1 else 256 - a), an integer; the weights sum
+  to 2^24.  Empty voxels hold 0, as in a texture cleared to zero.  The value is
+  (sum over c = 0..7, x fastest, of W_c v(b + c)) / 2^24 with the sum in FP64 in
+  that order, then rounded to FP32: every product is exact (a 24-bit integer
+  times an FP32 value), so the value does not depend on how the products are
+  formed.  A sample contributes only if a corner of non-zero weight is a site
+  (so at a voxel centre it is exactly the nearest-voxel sample).
 * Transfer: t = (v - offset) * scale in FP32; table entry e = floor(256 t)
   clamped to [0, 255] (0 for a NaN); entry e holds (r, g, b, a), straight alpha.
 * Compositing, front to back: C <- C + (1 - A) a (r, g, b), A <- A + (1 - A) a.
@@ -38,9 +48,42 @@ def transfer_index(values, scale, offset, entries=256):
     return e.astype(np.int64)
 
 
-def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offset=0.0):
+def _lookup(x, lo, hi, ext, skeys, order):
+    """Site index of integer points x [M, 3] (-1 where no site)."""
+    inside = np.all((x >= lo) & (x <= hi), axis=1)
+    s = np.full(x.shape[0], -1, dtype=np.int64)
+    if np.any(inside):
+        y = x[inside]
+        kx = ((y[:, 0] - lo[0]) * ext[1] + (y[:, 1] - lo[1])) * ext[2] + (y[:, 2] - lo[2])
+        pos = np.minimum(np.searchsorted(skeys, kx), len(skeys) - 1)
+        s[inside] = np.where(skeys[pos] == kx, order[pos], -1)
+    return s
+
+
+def trilinear(values, sites, frac):
+    """(value float32 [M], hit bool [M]) of samples whose 8 corners are `sites`
+    [M, 8] (corner c = x + 2y + 4z offsets, -1 for empty) with 8-bit fractions
+    `frac` [M, 3] in [0, 255]; hit: a corner of non-zero weight is a site."""
+    v = np.where(sites >= 0, np.asarray(values, dtype=np.float32)[np.maximum(sites, 0)],
+                 np.float32(0)).astype(np.float64)
+    acc = np.zeros(sites.shape[0])
+    hit = np.zeros(sites.shape[0], dtype=bool)
+    for c in range(8):
+        w = np.ones(sites.shape[0], dtype=np.int64)
+        for a in range(3):
+            fa = frac[:, a].astype(np.int64)
+            w = w * np.where((c >> a) & 1, fa, 256 - fa)
+        acc = acc + w.astype(np.float64) * v[:, c]  # exact product, FP64 sum in corner order
+        hit |= (w > 0) & (sites[:, c] >= 0)
+    return (acc * 2.0 ** -24).astype(np.float32), hit
+
+
+def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offset=0.0,
+                filter="nearest"):
     """Composited (r, g, b, a) [M, 4] (float64) of M rays with fixed-point start
     points `origins` [M, 3] and sample step `direction` [3]."""
+    if filter not in ("nearest", "trilinear"):
+        raise ValueError(filter)
     coords = np.asarray(coords, dtype=np.int64).reshape(-1, 3)
     lut = np.asarray(lut, dtype=np.float32).astype(np.float64)
     P0 = np.asarray(origins, dtype=np.int64).reshape(-1, 3)
@@ -61,18 +104,25 @@ def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offse
     order = np.argsort(keys)
     skeys = keys[order]
     entry = transfer_index(values, scale, offset, lut.shape[0])
+    corners = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.int64)
     for k in range(K):
-        x = (P0 + k * D + F // 2) >> 20  # floor division by F
-        inside = np.all((x >= lo) & (x <= hi), axis=1)
-        s = np.full(M, -1, dtype=np.int64)
-        if np.any(inside):
-            kx = key(x[inside])
-            pos = np.minimum(np.searchsorted(skeys, kx), len(skeys) - 1)
-            s[inside] = np.where(skeys[pos] == kx, order[pos], -1)
-        m = s >= 0
-        if not np.any(m):
-            continue
-        rgba = lut[entry[s[m]]]
+        P = P0 + k * D
+        if filter == "nearest":
+            s = _lookup((P + F // 2) >> 20, lo, hi, ext, skeys, order)  # floor division by F
+            m = s >= 0
+            if not np.any(m):
+                continue
+            e = entry[s[m]]
+        else:
+            b = P >> 20
+            frac = (P - (b << 20)) >> 12
+            cs = np.stack([_lookup(b + corners[c], lo, hi, ext, skeys, order) for c in range(8)],
+                          axis=1)
+            val, m = trilinear(values, cs, frac)
+            if not np.any(m):
+                continue
+            e = transfer_index(val[m], scale, offset, lut.shape[0])
+        rgba = lut[e]
         a = rgba[:, 3]
         keep = 1.0 - A[m]
         C[m] += (keep * a)[:, None] * rgba[:, :3]
@@ -81,10 +131,11 @@ def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offse
 
 
 def render(coords, values, view, lut, scale=1.0, offset=0.0):
-    """Image [H, W, 4] (float64) of `values` at site `coords` ([N, 3] integers)."""
+    """Image [H, W, 4] (float64) of `values` at site `coords` ([N, 3] integers);
+    view["filter"] is "nearest" (default) or "trilinear"."""
     W, H, K = int(view["width"]), int(view["height"]), int(view["steps"])
     O, R, U, D = (np.asarray(view[k], dtype=np.int64) for k in ("origin", "right", "up", "dir"))
     jj, ii = np.meshgrid(np.arange(H, dtype=np.int64), np.arange(W, dtype=np.int64), indexing="ij")
     P0 = O[None, :] + ii.reshape(-1, 1) * R[None, :] + jj.reshape(-1, 1) * U[None, :]
-    out = render_rays(coords, values, P0, D, K, lut, scale, offset)
+    out = render_rays(coords, values, P0, D, K, lut, scale, offset, view.get("filter", "nearest"))
     return out.reshape(H, W, 4)

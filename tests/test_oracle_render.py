@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle.render import F, render, transfer_index
+from oracle.render import F, render, transfer_index, trilinear
 from workloads.camera import axis_view, orbit_view, ramp_lut
 
 
@@ -118,3 +118,87 @@ def test_orbit_view_geometry():
     o = np.array(v["origin"]) + (np.array(v["right"]) * 1 + np.array(v["up"]) * 0.5)
     np.testing.assert_allclose(o / F, [60, 20, 30], atol=1e-6)
     assert math.isclose(np.linalg.norm(v["right"]) / F, 2.0, rel_tol=1e-6)
+
+
+# -- trilinear sampling -------------------------------------------------------------
+
+def test_trilinear_at_voxel_centres_is_nearest():
+    """Samples exactly at voxel centres weigh one corner only: the image is the
+    nearest-voxel image, bit for bit."""
+    r = 5
+    g = np.mgrid[-r:r + 1, -r:r + 1, -r:r + 1].reshape(3, -1).T
+    ball = g[np.sum(g * g, axis=1) <= r * r]
+    vals = np.random.default_rng(4).uniform(0, 1, len(ball)).astype(np.float32)
+    lut = np.random.default_rng(5).uniform(0, 1, (256, 4)).astype(np.float32)
+    lut[:, 3] *= 0.2
+    view = _view((-8 * F, -6 * F, -6 * F), (F, 0, 0), right=(0, F, 0), up=(0, 0, F), width=13,
+                 height=13, steps=17)
+    a = render(ball, vals, view, lut)
+    b = render(ball, vals, dict(view, filter="trilinear"), lut)
+    assert a[..., 3].max() > 0.5
+    np.testing.assert_array_equal(a, b)
+
+
+def test_trilinear_constant_field_is_exact():
+    """The eight weights are integers summing to 2^24, so a field that is the
+    same at all corners comes back exactly, at any fraction."""
+    rng = np.random.default_rng(6)
+    v = rng.uniform(-3, 3, 500).astype(np.float32)
+    sites = np.tile(np.arange(8), (500, 1))
+    frac = rng.integers(0, 256, (500, 3))
+    for k in range(500):
+        val, hit = trilinear(np.full(8, v[k], dtype=np.float32), sites[k:k + 1], frac[k:k + 1])
+        assert hit[0] and val[0] == v[k]
+
+
+def test_trilinear_matches_scipy_map_coordinates():
+    """An independent trilinear interpolation (scipy.ndimage, order 1) of the
+    dense array with zeros at empty voxels, at the 8-bit quantised positions."""
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(7)
+    dense = rng.uniform(0.1, 1.0, (6, 6, 6)).astype(np.float32)
+    dense[rng.uniform(size=dense.shape) < 0.3] = 0.0  # empty voxels
+    coords = np.argwhere(dense != 0)
+    values = dense[tuple(coords.T)]
+    idx = -np.ones(dense.shape, dtype=np.int64)
+    idx[tuple(coords.T)] = np.arange(len(coords))
+    base = rng.integers(0, 5, (400, 3))
+    frac = rng.integers(0, 256, (400, 3))
+    sites = np.stack([idx[base[:, 0] + (c & 1), base[:, 1] + ((c >> 1) & 1), base[:, 2] + (c >> 2)]
+                      for c in range(8)], axis=1)
+    val, hit = trilinear(values, sites, frac)
+    ref = map_coordinates(dense.astype(np.float64), (base + frac / 256.0).T, order=1)
+    np.testing.assert_allclose(val, ref, rtol=1e-6, atol=1e-7)
+    # a hit needs a site among the corners of non-zero weight
+    w = np.stack([np.prod([np.where((c >> a) & 1, frac[:, a], 256 - frac[:, a]) for a in range(3)],
+                          axis=0) for c in range(8)], axis=1)
+    assert np.array_equal(hit, np.any((w > 0) & (sites >= 0), axis=1))
+
+
+def test_trilinear_ramp_between_two_voxels():
+    """Between voxels 0 and 1 on the x axis the value is v0 + (v1 - v0) a / 256,
+    and half way to an empty voxel it is half the value."""
+    v0, v1 = np.float32(0.25), np.float32(0.875)
+    a = np.arange(256)
+    frac = np.stack([a, np.zeros_like(a), np.zeros_like(a)], axis=1)
+    sites = np.full((256, 8), -1)
+    sites[:, 0], sites[:, 1] = 0, 1
+    val, hit = trilinear(np.array([v0, v1]), sites, frac)
+    exact = (float(v0) * (256 - a) + float(v1) * a) / 256.0
+    assert hit.all() and np.array_equal(val, exact.astype(np.float32))
+    sites[:, 1] = -1
+    val, _ = trilinear(np.array([v0, v1]), sites, frac)
+    assert val[128] == v0 / 2
+
+
+def test_trilinear_samples_seeing_one_voxel():
+    """Steps of 1/8 from x = -2 past one voxel at 0: with trilinear filtering the
+    voxel carries weight for base voxel -1 at non-zero fractions (k = 9..15) and
+    for base voxel 0 (k = 16..23): 15 samples, against 8 for the nearest voxel.
+    With a table of constant opacity alpha the image is 1 - (1 - alpha)^15."""
+    a = 0.125
+    view = _view((-2 * F, 0, 0), (F // 8, 0, 0), steps=40)
+    near = render(np.array([[0, 0, 0]]), np.array([0.5]), view, _lut(a=a))
+    tri = render(np.array([[0, 0, 0]]), np.array([0.5]), dict(view, filter="trilinear"), _lut(a=a))
+    assert near[0, 0, 3] == pytest.approx(1 - (1 - a) ** 8, rel=1e-14)
+    assert tri[0, 0, 3] == pytest.approx(1 - (1 - a) ** 15, rel=1e-14)
