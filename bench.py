@@ -251,10 +251,20 @@ def render_run(lb, geom, size=1024, frames=20):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / frames
     lit = float((image[..., 3] > 0).float().mean())
-    log(f"[bench] render {size}x{size}: {ms:.3f} ms/frame")
+    tri = dict(view, filter="trilinear")
+    lb.render(speed, tri, lut, scale=1.0 / max(hi, 1e-30), image=image)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(frames):
+        lb.render(speed, tri, lut, scale=1.0 / max(hi, 1e-30), image=image)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_tri = e0.elapsed_time(e1) / frames
+    log(f"[bench] render {size}x{size}: {ms:.3f} ms/frame (nearest), {ms_tri:.3f} (trilinear)")
     return {"field": "speed", "width": size, "height": size, "steps": view["steps"],
             "step_lattice_units": 0.5, "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
-            "rays_per_s": size * size / (ms * 1e-3), "lit_fraction": lit}
+            "rays_per_s": size * size / (ms * 1e-3), "lit_fraction": lit,
+            "trilinear_ms_per_frame": ms_tri}
 
 
 def main():

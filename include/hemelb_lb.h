@@ -300,21 +300,32 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches);
  * A view gives fixed-point integer vectors, HEMELB_VIEW_FIX units per lattice
  * spacing: ray (i, j), 0 <= i < width, 0 <= j < height, starts at
  * P0 = origin + i * right + j * up and samples P_k = P0 + k * dir, k = 0 .. steps-1.
- * A sample takes the nearest voxel, x = floor((P_k + FIX/2) / FIX) per axis.  At a
- * fluid site with value v: t = (v - offset) * scale (FP32), table entry
+ * With filter HEMELB_FILTER_NEAREST a sample takes the nearest voxel,
+ * x = floor((P_k + FIX/2) / FIX) per axis, and contributes if x is a fluid site,
+ * with its value v.  With HEMELB_FILTER_TRILINEAR it filters as a 3D texture
+ * does: base voxel b = floor(P_k / FIX), 8-bit fraction a = floor((P_k - b FIX) /
+ * 2^12) per axis; corner b + c, c in {0,1}^3, weighs W_c = prod (c ? a : 256 - a)
+ * (integers summing to 2^24) and holds the site's value or 0 where there is no
+ * site; v = (float)(sum_c W_c v_c / 2^24), summed in FP64 in corner order c = x +
+ * 2y + 4z (each product is exact; zero-weight corners are not read).  The sample
+ * contributes if a corner of non-zero weight is a site.  A contributing sample
+ * of value v: t = (v - offset) * scale (FP32), table entry
  * e = clamp(floor(256 t), 0, 255) (0 for a NaN), (r, g, b, a) = lut[e] (straight
  * alpha), composited front to back in FP32: C += (1 - A) a (r, g, b),
- * A += (1 - A) a.  Samples in empty 4x4x4 blocks are skipped (they contribute
- * nothing).
+ * A += (1 - A) a.  Samples that can reach no site are skipped (whole 4x4x4
+ * blocks at a time).
  *   values  device float [N], one per site in caller order
  *   view    host; lut: host float [256][4]
  *   image   device float [height][width][4] = (C, A), written on the handle's stream
  * Errors: EINVAL if the handle was created without coords, for a NULL pointer,
- * width or height outside [1, 16384], steps outside [0, 2^24] or a non-finite
- * scale or offset; ENOMEM; EDEVICE.  The first call builds the block map of the
- * volume (device memory: 4 bytes per 4x4x4 block of the sites' bounding box).
+ * width or height outside [1, 16384], steps outside [0, 2^24], an unknown filter
+ * or a non-finite scale or offset; ENOMEM; EDEVICE.  The first call builds the
+ * block maps of the volume (device memory: about 5 bytes per 4x4x4 block of the
+ * sites' bounding box).
  */
 #define HEMELB_VIEW_FIX (1 << 20)
+#define HEMELB_FILTER_NEAREST 0
+#define HEMELB_FILTER_TRILINEAR 1
 typedef struct {
     int64_t origin[3];
     int64_t right[3];
@@ -326,6 +337,7 @@ typedef struct {
     float scale;
     float offset;
     const float* lut;
+    int32_t filter; /* HEMELB_FILTER_NEAREST or HEMELB_FILTER_TRILINEAR */
 } hemelb_view_t;
 
 int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image);

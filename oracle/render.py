@@ -22,8 +22,9 @@ formulas; this is the textbook emission-absorption ray marcher (front-to-back
   (sum over c = 0..7, x fastest, of W_c v(b + c)) / 2^24 with the sum in FP64 in
   that order, then rounded to FP32: every product is exact (a 24-bit integer
   times an FP32 value), so the value does not depend on how the products are
-  formed.  A sample contributes only if a corner of non-zero weight is a site
-  (so at a voxel centre it is exactly the nearest-voxel sample).
+  formed.  A corner of zero weight is not read.  A sample contributes only if a
+  corner of non-zero weight is a site (so at a voxel centre it is exactly the
+  nearest-voxel sample).
 * Transfer: t = (v - offset) * scale in FP32; table entry e = floor(256 t)
   clamped to [0, 255] (0 for a NaN); entry e holds (r, g, b, a), straight alpha.
 * Compositing, front to back: C <- C + (1 - A) a (r, g, b), A <- A + (1 - A) a.
@@ -73,8 +74,9 @@ def trilinear(values, sites, frac):
         for a in range(3):
             fa = frac[:, a].astype(np.int64)
             w = w * np.where((c >> a) & 1, fa, 256 - fa)
-        acc = acc + w.astype(np.float64) * v[:, c]  # exact product, FP64 sum in corner order
-        hit |= (w > 0) & (sites[:, c] >= 0)
+        use = (w > 0) & (sites[:, c] >= 0)  # a corner of zero weight is not read
+        acc = acc + np.where(use, w.astype(np.float64) * v[:, c], 0.0)  # exact, in corner order
+        hit |= use
     return (acc * 2.0 ** -24).astype(np.float32), hit
 
 

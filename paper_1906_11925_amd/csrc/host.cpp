@@ -264,6 +264,7 @@ struct hemelb_lb {
     // volume rendering: block map of the sites (built on the first render call)
     std::vector<int32_t> h_coords;  // [n][3] site coordinates in Morton order (when given)
     int32_t* r_grid = nullptr;
+    uint8_t* r_near = nullptr;
     hlb::BlockRec* r_rec = nullptr;
     float* r_vals = nullptr;
     float* r_lut = nullptr;
@@ -375,7 +376,7 @@ void release(hemelb_lb* h) {
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
                     h->d_opart,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
-                    h->is_pend,   h->r_grid,    h->r_rec,      h->r_vals,    h->r_lut,
+                    h->is_pend,   h->r_grid,    h->r_near,     h->r_rec,     h->r_vals,    h->r_lut,
                     h->is_lo,     h->is_hi,     h->d_vals};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -1156,8 +1157,21 @@ int build_render_volume(hemelb_lb_t h) {
         const int64_t gx = bc[3 * k] - lo[0], gy = bc[3 * k + 1] - lo[1], gz = bc[3 * k + 2] - lo[2];
         grid[(size_t)((gx * h->r_gdim[1] + gy) * h->r_gdim[2] + gz)] = (int32_t)k;
     }
+    // blocks within reach of a trilinear sample: near[B'] for B' = blo - 1 + h,
+    // h in [0, gdim] per axis, marks whether a block of B' + {0, 1}^3 holds a site
+    const int64_t nd[3] = {h->r_gdim[0] + 1, h->r_gdim[1] + 1, h->r_gdim[2] + 1};
+    std::vector<uint8_t> near((size_t)(nd[0] * nd[1] * nd[2]), 0);
+    for (size_t k = 0; k < rec.size(); ++k) {
+        const int64_t g[3] = {bc[3 * k] - lo[0], bc[3 * k + 1] - lo[1], bc[3 * k + 2] - lo[2]};
+        for (int c = 0; c < 8; ++c) {  // block g is reached from h = g + 1 - c
+            const int64_t x = g[0] + 1 - (c & 1), y = g[1] + 1 - ((c >> 1) & 1),
+                          z = g[2] + 1 - ((c >> 2) & 1);
+            near[(size_t)((x * nd[1] + y) * nd[2] + z)] = 1;
+        }
+    }
     int rc;
     if ((rc = dev_upload(h, &h->r_grid, grid, "render block map"))) return rc;
+    if ((rc = dev_upload(h, &h->r_near, near, "render reach map"))) return rc;
     if ((rc = dev_upload(h, &h->r_rec, rec, "render block records"))) return rc;
     if ((rc = dev_alloc(h, &h->r_vals, (size_t)std::max<int64_t>(n, 1), "render values"))) return rc;
     if ((rc = dev_alloc(h, &h->r_lut, 256 * 4, "render table"))) return rc;
@@ -1724,6 +1738,8 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
         return fail(HEMELB_EINVAL, "steps %d outside [0, 2^24]", view->steps);
     if (!std::isfinite(view->scale) || !std::isfinite(view->offset))
         return fail(HEMELB_EINVAL, "transfer scale and offset must be finite");
+    if (view->filter != HEMELB_FILTER_NEAREST && view->filter != HEMELB_FILTER_TRILINEAR)
+        return fail(HEMELB_EINVAL, "unknown filter %d", view->filter);
     for (int a = 0; a < 3; ++a)
         for (const int64_t v : {view->origin[a], view->right[a], view->up[a], view->dir[a]})
             if (v > ((int64_t)1 << 46) || v < -((int64_t)1 << 46))
@@ -1735,7 +1751,11 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
     HIP_TRY(hipMemcpyAsync(h->r_lut, view->lut, 256 * 4 * sizeof(float), hipMemcpyHostToDevice,
                            h->stream),
             "render table");
-    hlb::RenderVolume V{h->r_grid, h->r_rec, h->r_vals, {h->r_blo[0], h->r_blo[1], h->r_blo[2]},
+    hlb::RenderVolume V{h->r_grid,
+                        h->r_rec,
+                        h->r_vals,
+                        h->r_near,
+                        {h->r_blo[0], h->r_blo[1], h->r_blo[2]},
                         {h->r_gdim[0], h->r_gdim[1], h->r_gdim[2]}};
     hlb::RenderView v{};
     for (int a = 0; a < 3; ++a) {
@@ -1749,6 +1769,7 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
     v.steps = view->steps;
     v.scale = view->scale;
     v.offset = view->offset;
+    v.filter = view->filter;
     HIP_TRY(hlb::launch_render(V, v, h->r_lut, image, h->stream), "render");
     return HEMELB_OK;
 }

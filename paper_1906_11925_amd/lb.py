@@ -207,7 +207,8 @@ class LB:
     def render(self, values, view, lut, scale=1.0, offset=0.0, image=None):
         """Ray-marched image [H, W, 4] (float32 CUDA tensor) of per-site `values`
         (float32 CUDA tensor [N], caller order) seen through `view` (a dict of the
-        fixed-point vectors origin, right, up, dir and width, height, steps; see
+        fixed-point vectors origin, right, up, dir and width, height, steps, and
+        optionally filter: "nearest" (default) or "trilinear"; see
         include/hemelb_lb.h) with the RGBA colour table `lut` ([256, 4])."""
         torch = _torch()
         v = L.ViewT()
@@ -216,6 +217,8 @@ class LB:
                 getattr(v, name)[a] = int(view[name][a])
         v.width, v.height, v.steps = int(view["width"]), int(view["height"]), int(view["steps"])
         v.scale, v.offset = float(scale), float(offset)
+        f = view.get("filter", "nearest")
+        v.filter = L.FILTERS[f] if isinstance(f, str) else int(f)
         lut = np.ascontiguousarray(lut, dtype=np.float32)
         if lut.shape != (256, 4):
             raise ValueError("lut must be [256, 4]")

@@ -178,3 +178,103 @@ def test_render_errors():
     with pytest.raises(HemelbError) as ei:
         nocoords.render(t, orbit_view((9, 9, 31), 40, 0, 0, 4, 4), lut)
     assert "coordinates" in str(ei.value)
+
+
+# -- trilinear sampling ------------------------------------------------------------
+# The filtered value is the same bits on both sides (integer weights, exact FP64
+# products), so the sample set and every table entry match; only the FP32
+# compositing differs, as for the nearest voxel.
+
+@pytest.mark.parametrize("name", ["pipe", "aneurysm_half", "tree_small"])
+@pytest.mark.parametrize("angles", [(0, 0), (30, 20), (200, -35), (90, 89)])
+def test_trilinear_random_values_match_oracle(name, angles):
+    _gpu()
+    g = {"pipe": wl.pipe, "aneurysm_half": lambda: wl.aneurysm(half=True),
+         "tree_small": _tree_small}[name]()
+    vals = np.random.default_rng(8).uniform(0.0, 1.0, g.n_sites).astype(np.float32)
+    centre, size = _centre(g)
+    view = dict(orbit_view(centre, size, angles[0], angles[1], 48, 40, pixel=size / 40.0,
+                           step=0.37), filter="trilinear")
+    lut = ramp_lut(0.08)
+    lb = LB.from_geometry(g)
+    img = lb.render(torch.from_numpy(vals).cuda(), view, lut, scale=1.3, offset=0.05)
+    ref = oracle_render(g.coords, vals, view, lut, scale=1.3, offset=0.05)
+    assert ref[..., 3].max() > 0.05
+    _check(img, ref, view)
+    # filtering differs from the nearest voxel off the voxel centres
+    near = oracle_render(g.coords, vals, dict(view, filter="nearest"), lut, scale=1.3, offset=0.05)
+    assert not np.array_equal(near, ref)
+
+
+def test_trilinear_edge_views():
+    _gpu()
+    g = wl.aneurysm(half=True)
+    vals = np.random.default_rng(9).uniform(0.0, 1.0, g.n_sites).astype(np.float32)
+    t = torch.from_numpy(vals).cuda()
+    lut = ramp_lut(0.2)
+    lb = LB.from_geometry(g)
+    lo, hi = g.coords.min(axis=0), g.coords.max(axis=0)
+    low = g.coords[np.argmin(g.coords[:, 2])]  # a site of the lowest layer
+    views = [
+        # pointing away from the volume
+        {"origin": [-50 * FIX, 0, 0], "right": [0, FIX, 0], "up": [0, 0, FIX],
+         "dir": [-FIX, 0, 0], "width": 5, "height": 3, "steps": 100},
+        # no samples
+        dict(orbit_view((96, 80, 48), 150, 10, 10, 7, 5), steps=0),
+        # a standing ray between voxel centres inside the volume
+        {"origin": [int(g.coords[100, 0]) * FIX + FIX // 3, int(g.coords[100, 1]) * FIX + 5,
+                    int(g.coords[100, 2]) * FIX + FIX // 2], "right": [FIX, 0, 0],
+         "up": [0, FIX, 0], "dir": [0, 0, 0], "width": 3, "height": 2, "steps": 37},
+        # rays 0.4 below the lowest layer of sites: base voxel one below the sites,
+        # the corner above it carries weight 153/256
+        {"origin": [(int(low[0]) - 20) * FIX, (int(low[1]) - 8) * FIX + FIX // 3,
+                    (int(lo[2]) - 1) * FIX + 153 * 4096], "right": [0, FIX // 2, 0],
+         "up": [0, 0, 0], "dir": [FIX // 4, 0, 0], "width": 32, "height": 1, "steps": 160},
+        # one pixel; a ragged image wider than one workgroup of rays
+        orbit_view((96, 80, 48), 150, 45, 45, 1, 1, pixel=2.0, step=0.7),
+        orbit_view((96, 80, 48), 150, 300, -10, 37, 19, pixel=6.0, step=1.3),
+        # the whole box straight along an axis, samples between voxel centres
+        dict(axis_view(lo, hi, axis=1, pixel=3.0, step=0.45)),
+    ]
+    for k, view in enumerate(views):
+        view = dict(view, filter="trilinear")
+        img = lb.render(t, view, lut, scale=1.5, offset=0.1)
+        ref = oracle_render(g.coords, vals, view, lut, scale=1.5, offset=0.1)
+        if k == 3:
+            assert ref[..., 3].max() > 0  # the low-face rays do see sites
+        _check(img, ref, view)
+    assert np.all(lb.render(t, dict(views[0], filter="trilinear"), lut).cpu().numpy() == 0)
+
+
+def test_trilinear_full_size_tree_sampled_rays():
+    """The 5.6M-site tree through the trilinear filter; the oracle recomputes
+    128 seeded pixels (32 of them among the lit ones)."""
+    _gpu()
+    g = wl.config_geometry("tree1024")
+    vals = np.random.default_rng(12).uniform(0.0, 1.0, g.n_sites).astype(np.float32)
+    lb = LB.from_geometry(g, storage="f16")
+    view = dict(orbit_view((512, 512, 512), 900, 35, 25, 512, 512, pixel=1024 / 512 * 1.4,
+                           step=0.9), filter="trilinear")
+    lut = ramp_lut(0.05)
+    img = lb.render(torch.from_numpy(vals).cuda(), view, lut).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(13)
+    pix = rng.integers(0, 512, (96, 2))
+    lit = np.argwhere(img[..., 3] > 0)
+    pix = np.concatenate([pix, lit[rng.choice(len(lit), 32, replace=False)][:, ::-1]])
+    O, R, U = (np.asarray(view[k], dtype=np.int64) for k in ("origin", "right", "up"))
+    origins = O[None, :] + pix[:, :1] * R[None, :] + pix[:, 1:] * U[None, :]
+    ref = render_rays(g.coords, vals, origins, view["dir"], view["steps"], lut,
+                      filter="trilinear")
+    got = img[pix[:, 1], pix[:, 0]]
+    assert np.array_equal(got[:, 3] == 0, ref[:, 3] == 0)
+    assert np.abs(got - ref).max() <= _tol(view)
+
+
+def test_unknown_filter_is_rejected():
+    _gpu()
+    g = wl.pipe()
+    lb = LB.from_geometry(g)
+    t = torch.zeros(g.n_sites, dtype=torch.float32, device="cuda")
+    with pytest.raises(HemelbError) as ei:
+        lb.render(t, dict(orbit_view((9, 9, 31), 40, 0, 0, 4, 4), filter=2), ramp_lut())
+    assert ei.value.code == L.HEMELB_EINVAL
