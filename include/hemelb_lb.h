@@ -433,6 +433,26 @@ int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const i
                           const int64_t* steps, int64_t nseg);
 
 /*
+ * Store-all checkpointing, for problems whose whole trajectory fits in device
+ * memory (each state is q * pitch * sizeof(storage) bytes; 4001 states of the
+ * 199k-site half aneurysm in FP32 take 48 GB).  hemelb_lb_record allocates
+ * max_steps + 1 population buffers and copies the current state (time t0) into
+ * the first; each following step writes its new state into the next buffer
+ * instead of the handle's own, so the trajectory t0 .. t0 + max_steps stays on
+ * the device.  Every other call works as before; hemelb_lb_step beyond the
+ * record and hemelb_lb_set_state / _set_deviations during it return EORDER.
+ * hemelb_lb_adjoint_recorded runs the reverse sweep (after hemelb_lb_adjoint_begin)
+ * from the time the sweep has reached back to t0 over the recorded states, with
+ * no recomputation; the result equals that of the checkpointed calls bit for
+ * bit.  hemelb_lb_record_end copies the current and previous state back into the
+ * handle's own buffers and frees the record (no-op when not recording; waits).
+ * Errors: EINVAL, EORDER, ENOMEM, EDEVICE.
+ */
+int hemelb_lb_record(hemelb_lb_t h, int64_t max_steps);
+int hemelb_lb_adjoint_recorded(hemelb_lb_t h);
+int hemelb_lb_record_end(hemelb_lb_t h);
+
+/*
  * Gradients accumulated so far (waits).  dtheta: host doubles, for every velocity
  * iolet in id order its 1 + 2 n_harm derivatives (mean, cos_1..n, sin_1..n);
  * dalpha: host doubles [N] caller order.  Either may be NULL.  Errors: EORDER.

@@ -8,6 +8,9 @@ recomputes it onto a K+1-buffer tape and runs the hand-written adjoint
 kernels backwards through it; the FP64 gradients with respect to the velocity
 inlet's Fourier coefficients and the Brinkman field come back scaled by the
 incoming gradient of J.  Memory: ceil(N/K) checkpoints plus K+1 tape buffers.
+With K = 0 every state of the forward stays on the device instead (N + 1
+population buffers) and the backward needs no recomputation; the gradients are
+the same bits.
 """
 
 import dataclasses
@@ -35,11 +38,16 @@ class LBAdjointFn(torch.autograd.Function):
         th = theta.detach().to("cpu", torch.float64).numpy()
         lb.set_iolet(inlet, _with_coefficients(lb.iolets[inlet], th))
         lb.set_alpha(alpha.detach().to("cpu", torch.float32).numpy())
+        lb.record_end()
         lb.set_deviations(torch.zeros((lb.q, lb.n), dtype=torch.float32, device="cuda"), t=0)
         checkpoints = []
-        for t0 in range(0, steps, K):
-            checkpoints.append((t0, min(K, steps - t0), lb.get_state()[0].clone()))
-            lb.step(min(K, steps - t0))
+        if K == 0:
+            lb.record(steps)
+            lb.step(steps)
+        else:
+            for t0 in range(0, steps, K):
+                checkpoints.append((t0, min(K, steps - t0), lb.get_state()[0].clone()))
+                lb.step(min(K, steps - t0))
         J, _, _ = lb.objective_value()
         ctx.lb, ctx.inlet, ctx.K, ctx.checkpoints = lb, inlet, K, checkpoints
         ctx.alpha_meta = (alpha.dtype, alpha.device)
@@ -48,9 +56,15 @@ class LBAdjointFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         lb = ctx.lb
-        lb.adjoint_begin(ctx.K)
-        lb.adjoint_run(ctx.checkpoints)
-        dth, da = lb.adjoint_grads()
+        if ctx.K == 0:
+            lb.adjoint_begin(1)
+            lb.adjoint_recorded()
+            dth, da = lb.adjoint_grads()
+            lb.record_end()
+        else:
+            lb.adjoint_begin(ctx.K)
+            lb.adjoint_run(ctx.checkpoints)
+            dth, da = lb.adjoint_grads()
         g = float(gJ)
         dtheta = torch.from_numpy(dth[ctx.inlet] * g)
         dalpha = torch.from_numpy(np.asarray(da) * g).to(dtype=ctx.alpha_meta[0],

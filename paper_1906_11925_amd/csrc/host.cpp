@@ -300,6 +300,11 @@ struct hemelb_lb {
     // adjoint
     std::vector<void*> tape;  // K+1 population buffers of a recompute segment
     std::vector<void*> tape2;  // a second tape: recompute one segment while reversing another
+    // recorded trajectory: rec[m] holds the state at time rec_t0 + m; while recording,
+    // A[] point into rec and the handle's own population buffers wait in A_own
+    std::vector<void*> rec;
+    int64_t rec_t0 = -1;
+    void* A_own[2] = {nullptr, nullptr};
     struct Series {            // iolet values and Fourier basis of one segment
         double* vals = nullptr;
         double* basis = nullptr;
@@ -367,6 +372,12 @@ int dev_upload(hemelb_lb* h, T** p, const std::vector<T>& v, const char* what) {
 void release(hemelb_lb* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    if (h->rec_t0 >= 0) {  // A[] alias recorded buffers, freed below
+        h->A[0] = h->A_own[0];
+        h->A[1] = h->A_own[1];
+    }
+    for (void* p : h->rec)
+        if (p) (void)hipFree(p);
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
                     h->t16,       h->toff,      h->tlist,      h->brec,      h->gmask,
                     h->bnbr,      h->tblock,    h->g_slot,     h->gblob,     h->grp,
@@ -802,6 +813,13 @@ int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
 
 int do_step(hemelb_lb* h) {
     const hlb::Layout L = h->layout();
+    if (h->rec_t0 >= 0) {  // recording: the new state goes to the next recorded buffer
+        const int64_t m = h->t - h->rec_t0;
+        if (m + 1 >= (int64_t)h->rec.size())
+            return fail(HEMELB_EORDER, "the record holds %lld steps; end it before stepping on",
+                        (long long)h->rec.size() - 1);
+        h->A[h->cur ^ 1] = h->rec[m + 1];
+    }
     void* src = h->A[h->cur];
     void* dst = h->A[h->cur ^ 1];
     if (!h->ghosts_ready)
@@ -1664,6 +1682,7 @@ int hemelb_lb_get_state(hemelb_lb_t h, void* dst, int64_t* t) {
 int hemelb_lb_set_state(hemelb_lb_t h, const void* src, int64_t t) {
     if (!h || (!src && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
+    if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is being recorded");
     h->t = t;
     h->streamed = false;
     h->ghosts_ready = false;
@@ -1678,6 +1697,7 @@ int hemelb_lb_get_deviations(hemelb_lb_t h, float* dst) {
 int hemelb_lb_set_deviations(hemelb_lb_t h, const float* src, int64_t t) {
     if (!h || (!src && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
+    if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is being recorded");
     h->t = t;
     h->streamed = false;
     h->ghosts_ready = false;
@@ -2100,6 +2120,83 @@ static int adjoint_run_impl(hemelb_lb_t h, const void* const* checkpoints, const
 int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
                           const int64_t* steps, int64_t nseg) {
     return no_throw([&] { return adjoint_run_impl(h, checkpoints, t0, steps, nseg); });
+}
+
+static int record_impl(hemelb_lb_t h, int64_t max_steps) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (max_steps < 1) return fail(HEMELB_EINVAL, "max_steps must be >= 1");
+    if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is already being recorded");
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    const size_t popbytes = (size_t)h->q * h->slots * h->elem();
+    std::vector<void*> rec;
+    for (int64_t m = 0; m <= max_steps; ++m) {
+        void* p = nullptr;
+        const hipError_t e = hipMalloc(&p, popbytes);
+        if (e != hipSuccess) {
+            for (void* x : rec) (void)hipFree(x);
+            return hip_fail(e, "trajectory record");
+        }
+        rec.push_back(p);
+    }
+    // the current state (with its ghost slots) starts the record
+    HIP_TRY(hipMemcpyAsync(rec[0], h->A[h->cur], popbytes, hipMemcpyDeviceToDevice, h->stream),
+            "record start");
+    h->rec = std::move(rec);
+    h->device_bytes += (int64_t)(popbytes * h->rec.size());
+    h->A_own[0] = h->A[0];
+    h->A_own[1] = h->A[1];
+    h->A[h->cur] = h->rec[0];
+    h->rec_t0 = h->t;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_record(hemelb_lb_t h, int64_t max_steps) {
+    return no_throw([&] { return record_impl(h, max_steps); });
+}
+
+int hemelb_lb_record_end(hemelb_lb_t h) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (h->rec_t0 < 0) return HEMELB_OK;
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    const size_t popbytes = (size_t)h->q * h->slots * h->elem();
+    // the current and the previous state (observables re-gather the latter) move
+    // back into the handle's own buffers
+    for (int b = 0; b < 2; ++b)
+        if (h->A[b] != h->A_own[b])
+            HIP_TRY(hipMemcpyAsync(h->A_own[b], h->A[b], popbytes, hipMemcpyDeviceToDevice,
+                                   h->stream),
+                    "record end");
+    HIP_TRY(hipStreamSynchronize(h->stream), "sync");
+    h->A[0] = h->A_own[0];
+    h->A[1] = h->A_own[1];
+    for (void* p : h->rec) (void)hipFree(p);
+    h->device_bytes -= (int64_t)(popbytes * h->rec.size());
+    h->rec.clear();
+    h->rec_t0 = -1;
+    return HEMELB_OK;
+}
+
+static int adjoint_recorded_impl(hemelb_lb_t h) {
+    if (!h) return fail(HEMELB_EINVAL, "NULL handle");
+    if (h->adj_t < 0) return fail(HEMELB_EORDER, "call hemelb_lb_adjoint_begin first");
+    if (h->rec_t0 < 0) return fail(HEMELB_EORDER, "no trajectory is being recorded");
+    const int64_t steps = h->adj_t - h->rec_t0;
+    if (steps < 1 || h->adj_t > h->t)
+        return fail(HEMELB_EORDER, "the reverse sweep is at %lld; the record covers %lld .. %lld",
+                    (long long)h->adj_t, (long long)h->rec_t0, (long long)h->t);
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    h->ghosts_ready = false;
+    int rc = fill_segment_series(h, h->series[0], h->rec_t0, steps + 1, h->stream);
+    for (int64_t m = steps - 1; m >= 0 && !rc; --m)
+        rc = reverse_step(h, h->rec, h->series[0], h->rec_t0, m, h->stream);
+    if (!rc) rc = end_reverse(h, h->stream);
+    if (rc) return rc;
+    h->adj_t = h->rec_t0;
+    return HEMELB_OK;
+}
+
+int hemelb_lb_adjoint_recorded(hemelb_lb_t h) {
+    return no_throw([&] { return adjoint_recorded_impl(h); });
 }
 
 static int adjoint_grads_impl(hemelb_lb_t h, double* dtheta, double* dalpha) {

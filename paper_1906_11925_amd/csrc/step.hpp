@@ -39,9 +39,15 @@ __device__ inline void st_pop(T* p, T v) {
 
 // Incoming population of iolet link l (direction i) of a site whose stored
 // populations decode to vs, at time t (the definition the ghost-fill kernel applies).
+// Both the step kernel's epilogue and the ghost-fill kernel inline it; without
+// contraction every product and sum rounds on its own in both, so a state
+// restored from a checkpoint gets the same ghost values, bit for bit, as the
+// step that produced it (the moment sums it calls multiply only by 0 and +-1,
+// which is exact either way).
 template <int Q>
 __device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const float (&vs)[Q],
                                     int64_t t) {
+#pragma clang fp contract(off)
     using Lt = Lat<Q>;
     const int k = G.iolet[l];
     const double v = G.vals[(t - G.vals_t0) * G.n_iolets + k];

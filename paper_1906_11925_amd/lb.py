@@ -355,8 +355,9 @@ class LB:
 
     def adjoint_run(self, segments):
         """The whole reverse sweep: `segments` is a list of (t0, steps, checkpoint)
-        in forward order (checkpoint = raw state [Q, N] at time t0); recomputes
-        overlap the adjoint steps on a second stream (hemelb_lb_adjoint_run)."""
+        in forward order (checkpoint = raw state [Q, N] at time t0); each adjoint
+        step runs in one launch with a recompute step of the next earlier segment
+        (hemelb_lb_adjoint_run)."""
         keep = []
         for _, _, ck in segments:
             ck = ck.contiguous()
@@ -369,6 +370,18 @@ class LB:
         st = (ctypes.c_int64 * max(k, 1))(*[int(s[1]) for s in segments])
         L.check(self.lib.hemelb_lb_adjoint_run(self.h, ptrs, t0, st, k))
         self._keep = keep
+
+    def record(self, max_steps):
+        """Keep the next `max_steps` states on the device (hemelb_lb_record)."""
+        L.check(self.lib.hemelb_lb_record(self.h, int(max_steps)))
+
+    def adjoint_recorded(self):
+        """Reverse sweep over the recorded states, no recomputation."""
+        L.check(self.lib.hemelb_lb_adjoint_recorded(self.h))
+
+    def record_end(self):
+        """Free the recorded trajectory; the current state stays."""
+        L.check(self.lib.hemelb_lb_record_end(self.h))
 
     def theta_sizes(self):
         """Number of Fourier coefficients of each velocity iolet, in id order."""

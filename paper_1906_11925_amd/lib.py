@@ -110,6 +110,9 @@ _SIGS = {
     "hemelb_lb_adjoint_begin": (c_int32, [c_void_p, c_int64]),
     "hemelb_lb_adjoint_segment": (c_int32, [c_void_p, c_void_p, c_int64, c_int64]),
     "hemelb_lb_adjoint_run": (c_int32, [c_void_p, P(c_void_p), P(c_int64), P(c_int64), c_int64]),
+    "hemelb_lb_record": (c_int32, [c_void_p, c_int64]),
+    "hemelb_lb_adjoint_recorded": (c_int32, [c_void_p]),
+    "hemelb_lb_record_end": (c_int32, [c_void_p]),
     "hemelb_lb_adjoint_grads": (c_int32, [c_void_p, P(c_double), P(c_double)]),
     "hemelb_lb_get_adjoint": (c_int32, [c_void_p, c_void_p]),
     "hemelb_lb_last_error": (ctypes.c_char_p, []),

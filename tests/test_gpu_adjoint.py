@@ -20,8 +20,11 @@ torch = pytest.importorskip("torch")
 import workloads as wl  # noqa: E402
 from oracle.lbgk import LBGK  # noqa: E402
 from oracle.adjoint import Adjoint, Objective  # noqa: E402
-from paper_1906_11925_amd import LB  # noqa: E402
+from paper_1906_11925_amd import LB, HemelbError  # noqa: E402
+from paper_1906_11925_amd import lib as L  # noqa: E402
 from paper_1906_11925_amd.autograd import LBAdjointFn  # noqa: E402
+
+from lbtest import quantize  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -177,6 +180,93 @@ def test_autograd_function(tiny):
     assert _rel(alpha.grad.numpy() / 2.0, tiny["ahat"]) <= 1e-4
 
 
+def _gpu_run_recorded(P):
+    """Forward with every state kept on the device, then the reverse sweep over
+    them without recomputation."""
+    g, obj = P["g"], P["obj"]
+    lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32))
+    lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+    if P["d0"] is not None:
+        lb.set_deviations(torch.from_numpy(P["d0"]), t=0)
+    T = P["T"]
+    lb.record(T)
+    lb.step(T)
+    J = lb.objective_value()
+    q = lb.objective_flux()
+    lb.adjoint_begin(1)
+    lb.adjoint_recorded()
+    th, da = lb.adjoint_grads()
+    g0 = lb.get_adjoint().cpu().numpy().astype(np.float64)
+    lb.record_end()
+    return J, q, th[0], da, g0
+
+
+def test_recorded_sweep_is_bit_identical(tiny):
+    """Keeping every state instead of recomputing segments changes nothing: the
+    objective, the flux and every gradient are the same bits as the
+    checkpointed sweep's (and match the oracle through it)."""
+    _gpu()
+    a = _gpu_run_recorded(tiny)
+    b = _gpu_run(tiny, 7, pipelined=True)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    assert _rel(a[2], tiny["theta"]) <= 1e-4 and _rel(a[3], tiny["ahat"]) <= 1e-4
+
+
+def test_recording_keeps_the_forward_and_its_rules(tiny):
+    """While recording, states and observables are those of an unrecorded run;
+    after the record ends, stepping on continues from the same state.  Steps
+    past the record, state writes during it, and a recorded sweep without a
+    record are refused."""
+    _gpu()
+    g = tiny["g"]
+    d0 = torch.from_numpy(quantize(wl.random_deviations(15, g.n_sites, 2, 1e-3), 15, "f32"))
+    a = LB.from_geometry(g)
+    b = LB.from_geometry(g)
+    for lb in (a, b):
+        lb.set_deviations(d0, t=0)
+    a.record(6)
+    a.step(6)
+    b.step(6)
+    assert torch.equal(a.get_state()[0], b.get_state()[0])
+    for x, y in zip(a.observables(), b.observables()):
+        assert torch.equal(x, y)
+    for bad in (lambda: a.step(1), lambda: a.set_deviations(d0, t=0)):
+        with pytest.raises(HemelbError) as ei:
+            bad()
+        assert ei.value.code == L.HEMELB_EORDER
+    a.record_end()
+    a.step(5)
+    b.step(5)
+    assert torch.equal(a.get_state()[0], b.get_state()[0])
+    for x, y in zip(a.observables(), b.observables()):
+        assert torch.equal(x, y)
+    a.record_end()  # no record: nothing to do
+    with pytest.raises(HemelbError) as ei:
+        a.adjoint_recorded()
+    assert ei.value.code == L.HEMELB_EORDER
+
+
+def test_autograd_function_recording_every_state(tiny):
+    """K = 0 keeps every state: the same gradients, bit for bit, as K = 9."""
+    _gpu()
+    g, obj = tiny["g"], tiny["obj"]
+    io = g.iolets[0]
+    grads = []
+    for K in (9, 0):
+        lb = LB.from_geometry(g, alpha=tiny["alpha"].astype(np.float32))
+        lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+        theta = torch.tensor([io.mean, *io.cos, *io.sin], dtype=torch.float64, requires_grad=True)
+        alpha = torch.tensor(tiny["alpha"], dtype=torch.float64, requires_grad=True)
+        J = LBAdjointFn.apply(theta, alpha, lb, 0, tiny["T"], K)
+        J.backward()
+        grads.append((J.item(), theta.grad.numpy().copy(), alpha.grad.numpy().copy()))
+        lb.close()
+    assert grads[0][0] == grads[1][0]
+    assert np.array_equal(grads[0][1], grads[1][1]) and np.array_equal(grads[0][2], grads[1][2])
+
+
 def test_aneurysm_half_truncated_vs_oracle():
     """The adjoint workload's geometry (half-size aneurysm, pulsatile Ladd inlet,
     Brinkman field), truncated to 60 steps with a 20-step window, from a random
@@ -208,3 +298,40 @@ def test_d3q19_gradients_match_oracle_adjoint():
     (J, _, _), q, th, da, g0 = _gpu_run(P, 8)
     assert abs(J - P["J"]) <= 1e-5 * abs(P["J"])
     assert _rel(th, P["theta"]) <= 1e-4 and _rel(da, P["ahat"]) <= 1e-4 and _rel(g0, P["g0"]) <= 1e-4
+
+
+def test_recorded_sweep_is_bit_identical_on_the_pulsatile_aneurysm():
+    """The half aneurysm with its pulsatile inlet, the Brinkman field and the
+    dome shear term, 1000 steps: gradients from the recorded trajectory and from
+    200-step checkpoints are the same bits (recomputed segments restart from
+    restored states, whose ghost values equal those of the forward)."""
+    _gpu()
+    g = wl.aneurysm(half=True)
+    n = g.n_sites
+    c = g.coords.astype(np.float64)
+    C, R = g.info["centre"], g.info["radius"]
+    dome = ((c[:, 0] - C[0]) ** 2 + (c[:, 1] - C[1]) ** 2 + (c[:, 2] - C[2]) ** 2) < (R + 2) ** 2
+    alpha = np.random.default_rng(4).uniform(0.0, 0.01, n).astype(np.float32)
+    steps, K = 1000, 200
+    out = []
+    for recorded in (False, True):
+        lb = LB.from_geometry(g, alpha=alpha)
+        lb.set_objective(1, 0.001, dome, 1.0, (800, 1000))
+        lb.set_deviations(torch.zeros((lb.q, n), dtype=torch.float32, device="cuda"), t=0)
+        if recorded:
+            lb.record(steps)
+            lb.step(steps)
+            lb.adjoint_begin(1)
+            lb.adjoint_recorded()
+        else:
+            cks = []
+            for t0 in range(0, steps, K):
+                cks.append((t0, K, lb.get_state()[0].clone()))
+                lb.step(K)
+            lb.adjoint_begin(K)
+            lb.adjoint_run(cks)
+        th, da = lb.adjoint_grads()
+        out.append((th[0], da, lb.get_adjoint().cpu().numpy()))
+        lb.close()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
