@@ -439,8 +439,9 @@ int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const i
  * max_steps + 1 population buffers and copies the current state (time t0) into
  * the first; each following step writes its new state into the next buffer
  * instead of the handle's own, so the trajectory t0 .. t0 + max_steps stays on
- * the device.  Every other call works as before; hemelb_lb_step beyond the
- * record and hemelb_lb_set_state / _set_deviations during it return EORDER.
+ * the device.  Every other call works as before; a hemelb_lb_step request that
+ * would go past the record (nothing is done) and hemelb_lb_set_state /
+ * _set_deviations during it return EORDER.
  * hemelb_lb_adjoint_recorded runs the reverse sweep (after hemelb_lb_adjoint_begin)
  * from the time the sweep has reached back to t0 over the recorded states, with
  * no recomputation; the result equals that of the checkpointed calls bit for

@@ -1608,6 +1608,10 @@ int hemelb_lb_destroy(hemelb_lb_t h) {
 int hemelb_lb_step(hemelb_lb_t h, int64_t n) {
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (n < 0) return fail(HEMELB_EINVAL, "negative step count");
+    if (h->rec_t0 >= 0 && h->t + n > h->rec_t0 + (int64_t)h->rec.size() - 1)
+        return fail(HEMELB_EORDER, "the record ends at step %lld; %lld steps from %lld go past it",
+                    (long long)(h->rec_t0 + (int64_t)h->rec.size() - 1), (long long)n,
+                    (long long)h->t);
     HIP_TRY(hipSetDevice(h->device), "set device");
     constexpr int64_t kBatch = 1024;  // steps per table of iolet values
     for (int64_t k = 0; k < n; ++k) {

@@ -236,6 +236,7 @@ def test_recording_keeps_the_forward_and_its_rules(tiny):
         with pytest.raises(HemelbError) as ei:
             bad()
         assert ei.value.code == L.HEMELB_EORDER
+    assert torch.equal(a.get_state()[0], b.get_state()[0])  # the refused calls did nothing
     a.record_end()
     a.step(5)
     b.step(5)
