@@ -137,6 +137,14 @@ def load(build_if_missing=True):
             raise ImportError(f"{LIB_PATH} is not built")
         from . import build as _build
         _build.build()
+    # One HIP runtime per process: torch bundles its own, and the library must bind
+    # to it.  Loaded first, the library would bring in the system runtime, and
+    # torch would then load a second one beside it (two runtimes cannot share the
+    # device), so torch is imported before the library whenever it is installed.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -2,6 +2,7 @@
 invalid arguments on the host before any device work (CPU-only)."""
 
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -9,6 +10,8 @@ import pytest
 import workloads as wl
 from paper_1906_11925_amd import lib as L
 from paper_1906_11925_amd import links
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_exports_every_declared_symbol():
@@ -154,3 +157,20 @@ def test_reject_bad_objective_and_order():
     assert lib.hemelb_lb_set_objective(None, None) == L.HEMELB_EINVAL
     assert lib.hemelb_lb_adjoint_begin(None, 4) == L.HEMELB_EINVAL
     assert lib.hemelb_lb_adjoint_grads(None, None, None) == L.HEMELB_EINVAL
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library first (a host call before torch is imported) still
+    leaves a single HIP runtime mapped: torch's, which the library binds to."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1906_11925_amd import links\n"
+        "import workloads as wl\n"
+        "g = wl.pipe(); links(g.labels, g.shape, g.periodic, 15)\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"

@@ -13,6 +13,7 @@ FP16 storage <= 2e-3 after the run.
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -140,13 +141,13 @@ def test_one_step_f32_elementwise(name, q):
     assert np.abs(w - ow).max() < tol
 
 
-def _tol16(o, ref, f, storage, q):
+def _tol16(o, ref, f, storage, q, scaled=True):
     """Bound on one 16-bit step (see test_one_step_16bit_elementwise): the output
     rounding, FP32 collision error, and the rounding of the incoming iolet values
     at iolet sites.  Returns (bound, bound without the iolet term, sites without
     iolet links)."""
     ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
-    s = SCALES[q][:, None]
+    s = SCALES[q][:, None] if scaled else np.ones((q, 1))
     sub = 2.0 ** -25 / s if storage == "f16" else 0.0 * s
     ghost = o.links.kind == 2
     g_err = np.where(ghost, ulp * np.abs(f - o.lat.w[:, None]) + sub, 0.0).sum(axis=0)
@@ -176,6 +177,28 @@ def test_one_step_16bit_elementwise(storage):
     tol, plain_tol, plain = _tol16(o, ref, f, storage, q)
     assert np.all(np.abs(gpu - ref) <= tol)
     # away from iolets the bound is the plain rounding bound
+    assert np.all(np.abs(gpu - ref)[:, plain] <= plain_tol[:, plain])
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_one_step_16bit_unscaled_elementwise(storage):
+    """16-bit storage without the power-of-two scale (HEMELB_FLAG_NO_SCALE): the
+    same bound with scale 1, where FP16 keeps small deviations only as
+    subnormals (half-spacing 2^-25)."""
+    _gpu()
+    q = 15
+    g = wl.aneurysm(half=True)
+    o = LBGK(g, q)
+    d = quantize(wl.random_deviations(q, o.n, 6, 1e-3), q, storage, scale=False)
+    lb = LB.from_geometry(g, lattice=q, storage=storage, scale=False)
+    lb.set_deviations(torch.from_numpy(d), t=37)
+    lb.step(1)
+    gpu = _dev(lb)
+    lb.close()
+    A, f = o.step(o.lat.w[:, None] + d, 37)
+    ref = A - o.lat.w[:, None]
+    tol, plain_tol, plain = _tol16(o, ref, f, storage, q, scaled=False)
+    assert np.all(np.abs(gpu - ref) <= tol)
     assert np.all(np.abs(gpu - ref)[:, plain] <= plain_tol[:, plain])
 
 
@@ -628,3 +651,22 @@ def test_restore_and_continue_is_exact_over_a_pulsatile_run():
         if not torch.equal(b.get_state()[0], states[k + 1]):
             bad.append(200 * k)
     assert not bad, f"restored runs differ from t = {bad}"
+
+
+def test_host_call_before_torch_in_a_fresh_process():
+    """A program that calls the host library (links) before it ever imports
+    torch still steps on the GPU: the library binds to torch's HIP runtime."""
+    _gpu()
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import workloads as wl\n"
+        "from paper_1906_11925_amd import links, LB\n"
+        "g = wl.pipe(); coords, nbr = links(g.labels, g.shape, g.periodic, 15)\n"
+        "lb = LB(nbr, g.tau, coords=coords, iolets=list(g.iolets), site_weight=g.site_weight())\n"
+        "lb.step(10); p, u, w = lb.observables(); print(float(u.abs().max()))\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert float(r.stdout.strip().splitlines()[-1]) > 0
