@@ -11,8 +11,9 @@ formulas; this is the textbook emission-absorption ray marcher (front-to-back
 * Volume: the fluid sites; site s holds value v_s at integer coordinates x_s
   (voxel centres).  Every other point of space is empty (contributes nothing).
 * Rays: fixed-point integer vectors, F = 2^20 units per lattice spacing.  Ray
-  (i, j) starts at P0 = O + i R + j U; its samples are P_k = P0 + k D for
-  k = 0 .. K - 1.
+  (i, j) starts at P0 = O + i R + j U and has direction D_ij = D + i DR + j DU;
+  its samples are P_k = P0 + k D_ij for k = 0 .. K - 1 (DR = DU = 0: an
+  orthographic view; R = U = 0: a pinhole view from the eye O).
 * Sampling, nearest voxel: x = floor((P_k + F/2) / F) on each axis.
 * Sampling, trilinear (the filtering of a 3D texture): base voxel b = floor(P_k / F)
   and 8-bit fraction a = floor((P_k - b F) / 2^12) in [0, 255] on each axis (the
@@ -83,13 +84,14 @@ def trilinear(values, sites, frac):
 def render_rays(coords, values, origins, direction, steps, lut, scale=1.0, offset=0.0,
                 filter="nearest"):
     """Composited (r, g, b, a) [M, 4] (float64) of M rays with fixed-point start
-    points `origins` [M, 3] and sample step `direction` [3]."""
+    points `origins` [M, 3] and sample steps `direction` ([3], or [M, 3] for one
+    per ray)."""
     if filter not in ("nearest", "trilinear"):
         raise ValueError(filter)
     coords = np.asarray(coords, dtype=np.int64).reshape(-1, 3)
     lut = np.asarray(lut, dtype=np.float32).astype(np.float64)
     P0 = np.asarray(origins, dtype=np.int64).reshape(-1, 3)
-    D = np.asarray(direction, dtype=np.int64)
+    D = np.asarray(direction, dtype=np.int64).reshape(-1, 3)  # [1, 3] or [M, 3]
     M, K = P0.shape[0], int(steps)
     C = np.zeros((M, 3))
     A = np.zeros(M)
@@ -137,7 +139,11 @@ def render(coords, values, view, lut, scale=1.0, offset=0.0):
     view["filter"] is "nearest" (default) or "trilinear"."""
     W, H, K = int(view["width"]), int(view["height"]), int(view["steps"])
     O, R, U, D = (np.asarray(view[k], dtype=np.int64) for k in ("origin", "right", "up", "dir"))
+    DR = np.asarray(view.get("dir_right", (0, 0, 0)), dtype=np.int64)
+    DU = np.asarray(view.get("dir_up", (0, 0, 0)), dtype=np.int64)
     jj, ii = np.meshgrid(np.arange(H, dtype=np.int64), np.arange(W, dtype=np.int64), indexing="ij")
-    P0 = O[None, :] + ii.reshape(-1, 1) * R[None, :] + jj.reshape(-1, 1) * U[None, :]
-    out = render_rays(coords, values, P0, D, K, lut, scale, offset, view.get("filter", "nearest"))
+    i, j = ii.reshape(-1, 1), jj.reshape(-1, 1)
+    P0 = O[None, :] + i * R[None, :] + j * U[None, :]
+    Dij = D[None, :] + i * DR[None, :] + j * DU[None, :]
+    out = render_rays(coords, values, P0, Dij, K, lut, scale, offset, view.get("filter", "nearest"))
     return out.reshape(H, W, 4)

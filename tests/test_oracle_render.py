@@ -202,3 +202,46 @@ def test_trilinear_samples_seeing_one_voxel():
     tri = render(np.array([[0, 0, 0]]), np.array([0.5]), dict(view, filter="trilinear"), _lut(a=a))
     assert near[0, 0, 3] == pytest.approx(1 - (1 - a) ** 8, rel=1e-14)
     assert tri[0, 0, 3] == pytest.approx(1 - (1 - a) ** 15, rel=1e-14)
+
+
+# -- per-ray directions (pinhole views) ---------------------------------------------
+
+def test_per_ray_directions_by_hand():
+    """Three rays from one eye at x = -4, directions (1/2, -1/8 + i/8, 0) for
+    pixel i, through a column of voxels (0, y, 0), y = -2..2, with distinct
+    values and an opaque table: each pixel shows the first voxel its ray meets,
+    which is (0, i - 1, 0) (sample k = 7 lands at x = -1/2, y = -7/8 + 7 i / 8)."""
+    col = np.array([[0, y, 0] for y in range(-2, 3)])
+    vals = np.array([0.0, 0.25, 0.5, 0.75, 0.99], dtype=np.float32)  # entries 0, 64, 128, 192, 253
+    lut = np.zeros((256, 4), dtype=np.float32)
+    lut[:, 0] = np.arange(256)
+    lut[:, 3] = 1.0
+    view = {"origin": [-4 * F, 0, 0], "right": [0, 0, 0], "up": [0, 0, 0],
+            "dir": [F // 2, -F // 8, 0], "dir_right": [0, F // 8, 0], "dir_up": [0, 0, 0],
+            "width": 3, "height": 1, "steps": 20}
+    img = render(col, vals, view, lut)
+    assert list(img[0, :, 0]) == [64.0, 128.0, 192.0]
+    assert np.all(img[0, :, 3] == 1.0)
+
+
+def test_zero_direction_spread_is_the_orthographic_view():
+    r = 4
+    g = np.mgrid[-r:r + 1, -r:r + 1, -r:r + 1].reshape(3, -1).T
+    ball = g[np.sum(g * g, axis=1) <= r * r]
+    vals = np.random.default_rng(8).uniform(0, 1, len(ball)).astype(np.float32)
+    v = orbit_view((0, 0, 0), 10, 30, 20, 9, 7, pixel=1.1, step=0.4)
+    a = render(ball, vals, v, ramp_lut(0.2))
+    b = render(ball, vals, dict(v, dir_right=[0, 0, 0], dir_up=[0, 0, 0]), ramp_lut(0.2))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_perspective_view_geometry():
+    from workloads.camera import perspective_view
+    v = perspective_view((10, 20, 30), 50, 0, 0, 5, 5, fov=40, step=0.5)
+    assert v["right"] == [0, 0, 0] and v["up"] == [0, 0, 0]
+    np.testing.assert_allclose(np.array(v["origin"]) / F, [60, 20, 30], atol=1e-6)
+    centre = np.array(v["dir"]) + 2 * np.array(v["dir_right"]) + 2 * np.array(v["dir_up"])
+    np.testing.assert_allclose(centre / F, [-0.5, 0, 0], atol=1e-5)  # the central ray
+    # the edge rays open at the field of view
+    top = np.array(v["dir"]) + 2 * np.array(v["dir_right"]) + 5 * np.array(v["dir_up"]) - np.array(v["dir_up"]) / 2
+    assert math.degrees(math.atan2(top[2], -top[0])) == pytest.approx(20.0, abs=0.01)

@@ -5,7 +5,9 @@ zoom, model rotation, and the scale and offset of the transfer function.  It is
 handed to the renderer as fixed-point integer vectors, FIX units per lattice
 spacing, so that every sample position along every ray is an exact integer:
 ray (i, j) starts at origin + i * right + j * up and its k-th sample lies at
-that point + k * dir.
+that point + k * (dir + i * dir_right + j * dir_up).  Orthographic views have
+dir_right = dir_up = 0; a pinhole (perspective) view starts every ray at the eye
+(right = up = 0) and spreads the directions instead.
 
 This module only turns camera parameters into those integers and builds colour
 tables; the sampling, transfer and compositing are the renderer's.
@@ -49,6 +51,33 @@ def orbit_view(center, distance, azimuth, elevation, width, height, pixel=1.0, s
 
     return {"origin": fix(origin), "right": fix(r * pixel), "up": fix(u * pixel),
             "dir": fix(d * step), "width": int(width), "height": int(height), "steps": int(steps)}
+
+
+def perspective_view(center, distance, azimuth, elevation, width, height, fov=40.0, step=0.5,
+                     steps=None):
+    """Pinhole view of `center` from an eye `distance` lattice units away in the
+    direction given by `azimuth` and `elevation` (degrees, as orbit_view), with a
+    vertical field of view of `fov` degrees.  The central ray marches `step`
+    lattice units per sample; the others the same parameter step along their
+    (slightly longer) direction.  `steps` defaults to twice the distance."""
+    az, el = math.radians(azimuth), math.radians(elevation)
+    toward = np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+    d = -toward
+    world_up = np.array([0.0, 0.0, 1.0]) if abs(toward[2]) < 0.99 else np.array([0.0, 1.0, 0.0])
+    r = _unit(np.cross(d, world_up))
+    u = np.cross(r, d)
+    eye = np.asarray(center, dtype=np.float64) + toward * distance
+    s = 2.0 * math.tan(math.radians(fov) / 2.0) / height  # image-plane units per pixel at depth 1
+    d0 = d - r * s * (width - 1) / 2.0 - u * s * (height - 1) / 2.0
+    if steps is None:
+        steps = int(math.ceil(2.0 * distance / step))
+
+    def fix(v):
+        return [int(x) for x in np.rint(np.asarray(v) * FIX).astype(np.int64)]
+
+    return {"origin": fix(eye), "right": [0, 0, 0], "up": [0, 0, 0], "dir": fix(d0 * step),
+            "dir_right": fix(r * s * step), "dir_up": fix(u * s * step), "width": int(width),
+            "height": int(height), "steps": int(steps)}
 
 
 def axis_view(lo, hi, axis=0, pixel=1.0, step=0.5):
