@@ -299,7 +299,9 @@ int hemelb_lb_kernel_time(hemelb_lb_t h, double* ms, int64_t* launches);
  *
  * A view gives fixed-point integer vectors, HEMELB_VIEW_FIX units per lattice
  * spacing: ray (i, j), 0 <= i < width, 0 <= j < height, starts at
- * P0 = origin + i * right + j * up and samples P_k = P0 + k * dir, k = 0 .. steps-1.
+ * P0 = origin + i * right + j * up and samples P_k = P0 + k * D, k = 0 .. steps-1,
+ * with D = dir + i * dir_right + j * dir_up (dir_right = dir_up = 0: an
+ * orthographic view; right = up = 0: a pinhole view from the eye at origin).
  * With filter HEMELB_FILTER_NEAREST a sample takes the nearest voxel,
  * x = floor((P_k + FIX/2) / FIX) per axis, and contributes if x is a fluid site,
  * with its value v.  With HEMELB_FILTER_TRILINEAR it filters as a 3D texture
@@ -338,6 +340,8 @@ typedef struct {
     float offset;
     const float* lut;
     int32_t filter; /* HEMELB_FILTER_NEAREST or HEMELB_FILTER_TRILINEAR */
+    int64_t dir_right[3];
+    int64_t dir_up[3];
 } hemelb_view_t;
 
 int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image);

@@ -1765,7 +1765,8 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
     if (view->filter != HEMELB_FILTER_NEAREST && view->filter != HEMELB_FILTER_TRILINEAR)
         return fail(HEMELB_EINVAL, "unknown filter %d", view->filter);
     for (int a = 0; a < 3; ++a)
-        for (const int64_t v : {view->origin[a], view->right[a], view->up[a], view->dir[a]})
+        for (const int64_t v : {view->origin[a], view->right[a], view->up[a], view->dir[a],
+                                view->dir_right[a], view->dir_up[a]})
             if (v > ((int64_t)1 << 46) || v < -((int64_t)1 << 46))
                 return fail(HEMELB_EINVAL, "view vector component beyond 2^46 fixed-point units");
     HIP_TRY(hipSetDevice(h->device), "set device");
@@ -1787,6 +1788,8 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
         v.right[a] = view->right[a];
         v.up[a] = view->up[a];
         v.dir[a] = view->dir[a];
+        v.dir_right[a] = view->dir_right[a];
+        v.dir_up[a] = view->dir_up[a];
     }
     v.width = view->width;
     v.height = view->height;

@@ -69,9 +69,12 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
     const int32_t i = (int32_t)(blockIdx.x * kRayTile + threadIdx.x % kRayTile);
     const int32_t j = (int32_t)(blockIdx.y * kRayTile + threadIdx.x / kRayTile);
     if (i >= v.width || j >= v.height) return;
-    int64_t P0[3];
+    int64_t P0[3], D[3];  // start and step of ray (i, j)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) P0[a] = v.origin[a] + (int64_t)i * v.right[a] + (int64_t)j * v.up[a];
+    for (int a = 0; a < 3; ++a) {
+        P0[a] = v.origin[a] + (int64_t)i * v.right[a] + (int64_t)j * v.up[a];
+        D[a] = v.dir[a] + (int64_t)i * v.dir_right[a] + (int64_t)j * v.dir_up[a];
+    }
 
     // samples that can reach a site: on each axis P must lie in
     // [4 lo FIX - FIX/2, 4 (lo + dim) FIX - FIX/2) for the nearest voxel, and in
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
         const int64_t lo = TRI ? (4 * (int64_t)V.blo[a] - 1) * kFix : 4 * (int64_t)V.blo[a] * kFix - kFix / 2;
         const int64_t hi = TRI ? 4 * ((int64_t)V.blo[a] + V.gdim[a]) * kFix
                                : 4 * ((int64_t)V.blo[a] + V.gdim[a]) * kFix - kFix / 2;  // exclusive
-        const int64_t d = v.dir[a];
+        const int64_t d = D[a];
         if (d == 0) {
             if (P0[a] < lo || P0[a] >= hi) k1 = 0;
         } else if (d > 0) {
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
             bool in = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int64_t P = P0[a] + k * v.dir[a];
+                const int64_t P = P0[a] + k * D[a];
                 b[a] = P >> 20;                               // base voxel (floor)
                 fr[a] = (int)((P - b[a] * kFix) >> 12);        // 8-bit fraction
                 B[a] = b[a] >> 2;
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
                 int64_t next = k1;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const int64_t d = v.dir[a];
+                    const int64_t d = D[a];
                     if (d > 0)
                         next = min(next, ceil_div_pos((4 * B[a] + 4) * kFix - P0[a], d));
                     else if (d < 0)
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
         bool in = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            x[a] = (P0[a] + k * v.dir[a] + kFix / 2) >> 20;  // nearest voxel (floor)
+            x[a] = (P0[a] + k * D[a] + kFix / 2) >> 20;  // nearest voxel (floor)
             b[a] = x[a] >> 2;
             const int64_t g = b[a] - V.blo[a];
             in = in && g >= 0 && g < V.gdim[a];
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kRayTile* kRayTile) void k_render(RenderVolume V, R
             int64_t next = k1;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int64_t d = v.dir[a];
+                const int64_t d = D[a];
                 if (d > 0) {
                     const int64_t e = (4 * b[a] + 4) * kFix - kFix / 2;
                     next = min(next, ceil_div_pos(e - P0[a], d));

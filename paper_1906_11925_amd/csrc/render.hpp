@@ -29,6 +29,7 @@ struct RenderView {
     int64_t right[3];
     int64_t up[3];
     int64_t dir[3];
+    int64_t dir_right[3], dir_up[3];  // ray (i, j) steps dir + i dir_right + j dir_up
     int32_t width, height, steps;
     float scale, offset;
     int32_t filter;  // 0: nearest voxel, 1: trilinear

@@ -208,13 +208,15 @@ class LB:
         """Ray-marched image [H, W, 4] (float32 CUDA tensor) of per-site `values`
         (float32 CUDA tensor [N], caller order) seen through `view` (a dict of the
         fixed-point vectors origin, right, up, dir and width, height, steps, and
-        optionally filter: "nearest" (default) or "trilinear"; see
+        optionally dir_right and dir_up (per-pixel direction increments: a pinhole
+        view) and filter: "nearest" (default) or "trilinear"; see
         include/hemelb_lb.h) with the RGBA colour table `lut` ([256, 4])."""
         torch = _torch()
         v = L.ViewT()
-        for name in ("origin", "right", "up", "dir"):
+        for name in ("origin", "right", "up", "dir", "dir_right", "dir_up"):
+            vec = view.get(name, (0, 0, 0)) if name.startswith("dir_") else view[name]
             for a in range(3):
-                getattr(v, name)[a] = int(view[name][a])
+                getattr(v, name)[a] = int(vec[a])
         v.width, v.height, v.steps = int(view["width"]), int(view["height"]), int(view["steps"])
         v.scale, v.offset = float(scale), float(offset)
         f = view.get("filter", "nearest")

@@ -59,7 +59,8 @@ class InfoT(ctypes.Structure):
 class ViewT(ctypes.Structure):
     _fields_ = [("origin", c_int64 * 3), ("right", c_int64 * 3), ("up", c_int64 * 3),
                 ("dir", c_int64 * 3), ("width", c_int32), ("height", c_int32), ("steps", c_int32),
-                ("scale", c_float), ("offset", c_float), ("lut", P(c_float)), ("filter", c_int32)]
+                ("scale", c_float), ("offset", c_float), ("lut", P(c_float)), ("filter", c_int32),
+                ("dir_right", c_int64 * 3), ("dir_up", c_int64 * 3)]
 
 
 VIEW_FIX = 1 << 20

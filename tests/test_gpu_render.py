@@ -278,3 +278,60 @@ def test_unknown_filter_is_rejected():
     with pytest.raises(HemelbError) as ei:
         lb.render(t, dict(orbit_view((9, 9, 31), 40, 0, 0, 4, 4), filter=2), ramp_lut())
     assert ei.value.code == L.HEMELB_EINVAL
+
+
+# -- pinhole (perspective) views ------------------------------------------------------
+
+@pytest.mark.parametrize("filt", ["nearest", "trilinear"])
+@pytest.mark.parametrize("name", ["pipe", "aneurysm_half", "tree_small"])
+@pytest.mark.parametrize("angles", [(25, 15), (250, -40)])
+def test_perspective_views_match_oracle(name, angles, filt):
+    _gpu()
+    from workloads.camera import perspective_view
+    g = {"pipe": wl.pipe, "aneurysm_half": lambda: wl.aneurysm(half=True),
+         "tree_small": _tree_small}[name]()
+    vals = np.random.default_rng(14).uniform(0.0, 1.0, g.n_sites).astype(np.float32)
+    centre, size = _centre(g)
+    view = dict(perspective_view(centre, 1.2 * size, angles[0], angles[1], 44, 36, fov=45,
+                                 step=0.41), filter=filt)
+    lut = ramp_lut(0.08)
+    lb = LB.from_geometry(g)
+    img = lb.render(torch.from_numpy(vals).cuda(), view, lut, scale=1.2, offset=0.02)
+    ref = oracle_render(g.coords, vals, view, lut, scale=1.2, offset=0.02)
+    assert ref[..., 3].max() > 0.05
+    _check(img, ref, view)
+
+
+def test_perspective_full_size_tree_sampled_rays():
+    """A pinhole view of the 5.6M-site tree; the oracle recomputes 128 seeded
+    pixels (32 among the lit ones), each with its own direction."""
+    _gpu()
+    from workloads.camera import perspective_view
+    g = wl.config_geometry("tree1024")
+    vals = np.random.default_rng(15).uniform(0.0, 1.0, g.n_sites).astype(np.float32)
+    lb = LB.from_geometry(g, storage="f16")
+    view = perspective_view((512, 512, 512), 1400, 35, 25, 512, 512, fov=50, step=1.0)
+    lut = ramp_lut(0.05)
+    img = lb.render(torch.from_numpy(vals).cuda(), view, lut).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(16)
+    pix = rng.integers(0, 512, (96, 2))
+    lit = np.argwhere(img[..., 3] > 0)
+    pix = np.concatenate([pix, lit[rng.choice(len(lit), 32, replace=False)][:, ::-1]])
+    O, D, DR, DU = (np.asarray(view[k], dtype=np.int64) for k in ("origin", "dir", "dir_right", "dir_up"))
+    origins = np.repeat(O[None, :], len(pix), axis=0)
+    dirs = D[None, :] + pix[:, :1] * DR[None, :] + pix[:, 1:] * DU[None, :]
+    ref = render_rays(g.coords, vals, origins, dirs, view["steps"], lut)
+    got = img[pix[:, 1], pix[:, 0]]
+    assert np.array_equal(got[:, 3] == 0, ref[:, 3] == 0)
+    assert np.abs(got - ref).max() <= _tol(view)
+
+
+def test_direction_spread_beyond_range_is_rejected():
+    _gpu()
+    g = wl.pipe()
+    lb = LB.from_geometry(g)
+    t = torch.zeros(g.n_sites, dtype=torch.float32, device="cuda")
+    view = dict(orbit_view((9, 9, 31), 40, 0, 0, 4, 4), dir_right=[0, 1 << 47, 0])
+    with pytest.raises(HemelbError) as ei:
+        lb.render(t, view, ramp_lut())
+    assert ei.value.code == L.HEMELB_EINVAL
