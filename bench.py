@@ -310,6 +310,8 @@ def main():
                     help="also compute velocity/pressure/WSS every k steps inside the timed run")
     ap.add_argument("--addressing", default="auto", choices=["auto", "blocks", "table16", "table32"],
                     help="how the kernels find upstream neighbours (auto: blocks where they apply)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only the adjoint workload (checkpointed and recorded sweeps), one JSON line")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed stream+collide steps (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -326,6 +328,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.adjoint:
+        log("[bench] adjoint workload only")
+        out = adjoint_run()
+        print(json.dumps({k: v for k, v in out.items() if k != "dJ_dtheta"}), flush=True)
+        return
 
     log(f"[bench] building workload {args.workload}")
     t0 = time.perf_counter()
