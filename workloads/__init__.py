@@ -22,6 +22,7 @@ from .geometry import (  # noqa: F401
     tree,
     couette,
     channel,
+    duct,
     closed_box,
     periodic_box,
     config_geometry,

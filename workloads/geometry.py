@@ -417,6 +417,19 @@ def channel(H=8, L=48, Lx=4, rho_in=1.001, rho_out=1.0, tau=0.6):
                     tau=tau, info=dict(H=H, L=L), inside=inside)
 
 
+def duct(X=3, Y=4, L=10, rho_in=1.0, rho_out=1.0, tau=0.7):
+    """Box periodic in x and y, fluid 0 <= z < L, with a pressure iolet beyond
+    z = 0 (iolet 0) and one beyond z = L-1 (iolet 1); no walls."""
+    shape = (X, Y, L)
+    lab = _empty(shape)
+    lab[1:X + 1, 1:Y + 1, 1:L + 1] = FLUID
+    lab[1:X + 1, 1:Y + 1, 0] = 2
+    lab[1:X + 1, 1:Y + 1, L + 1] = 3
+    return Geometry("duct", shape, lab, periodic=(True, True, False),
+                    iolets=[Iolet("pressure", mean=rho_in), Iolet("pressure", mean=rho_out)],
+                    tau=tau, info=dict(L=L))
+
+
 def closed_box(X=6, Y=5, Z=7, tau=0.7):
     """All sites of the box are fluid, surrounded by resting walls."""
     shape = (X, Y, Z)
