@@ -215,12 +215,20 @@ int hemelb_lb_destroy(hemelb_lb_t h);
 /*
  * Enqueue n >= 0 time steps (Section 2: propagation + collision; Table 3 counts
  * these as site updates) on the handle's stream and return without waiting.
- * Each step launches an iolet ghost fill (if the geometry has iolets) and one
- * fused stream+collide kernel.  Errors: EINVAL (n < 0), ECANCELLED, EDEVICE.
+ * Each step is one fused stream+collide launch, whose epilogue also writes the
+ * incoming iolet populations of the next step; a separate ghost fill runs only
+ * before the first step after create, set_state or set_deviations.  Once per
+ * 1024 steps a small kernel tabulates the iolet time series.
+ * Errors: EINVAL (n < 0), EORDER (past the end of a record), ECANCELLED, EDEVICE.
  */
 int hemelb_lb_step(hemelb_lb_t h, int64_t n);
 
-/* Wait for the handle's queued work; reports EDIVERGED if a check failed. */
+/*
+ * Wait for the handle's queued work; with checks on, reports EDIVERGED if a check
+ * (or a hemelb_lb_totals call) has met a non-finite value since the state was last
+ * set.  The report repeats on every sync until set_state / set_deviations installs
+ * a new state, which clears it.
+ */
 int hemelb_lb_sync(hemelb_lb_t h);
 
 /* Run a divergence check (non-finite density or momentum) every `every` steps (0: off). */
@@ -233,8 +241,8 @@ int hemelb_lb_cancel(hemelb_lb_t h);
 int hemelb_lb_set_stream(hemelb_lb_t h, void* stream);
 
 /*
- * Observables of the current time ("lattice properties computed and cached",
- * Section 3.C.2), from the pre-collision populations of the last step (from the
+ * Observables of the current time (the lattice properties that Section 3.C.2
+ * computes and caches for output), from the pre-collision populations of the last step (from the
  * stored populations when no step has run since create/set_state):
  *   p    float [N] device, pressure deviation (rho - 1) / 3 from the reference
  *        density 1 (lattice units; p = rho/3 minus 1/3, kept as a deviation so

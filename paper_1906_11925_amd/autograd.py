@@ -10,7 +10,9 @@ inlet's Fourier coefficients and the Brinkman field come back scaled by the
 incoming gradient of J.  Memory: ceil(N/K) checkpoints plus K+1 tape buffers.
 With K = 0 every state of the forward stays on the device instead (N + 1
 population buffers) and the backward needs no recomputation; the gradients are
-the same bits.
+the same bits.  That record is kept only when a gradient is wanted; it is freed
+by the backward, or by the handle's next forward, or by `lb.record_end()` when
+the result is dropped without a backward.
 """
 
 import dataclasses
@@ -41,7 +43,10 @@ class LBAdjointFn(torch.autograd.Function):
         lb.record_end()
         lb.set_deviations(torch.zeros((lb.q, lb.n), dtype=torch.float32, device="cuda"), t=0)
         checkpoints = []
-        if K == 0:
+        wanted = any(ctx.needs_input_grad[:2])
+        if not wanted:
+            lb.step(steps)
+        elif K == 0:
             lb.record(steps)
             lb.step(steps)
         else:
@@ -51,6 +56,7 @@ class LBAdjointFn(torch.autograd.Function):
         J, _, _ = lb.objective_value()
         ctx.lb, ctx.inlet, ctx.K, ctx.checkpoints = lb, inlet, K, checkpoints
         ctx.alpha_meta = (alpha.dtype, alpha.device)
+        ctx.theta_meta = (theta.dtype, theta.device)
         return torch.tensor(J, dtype=torch.float64)
 
     @staticmethod
@@ -66,7 +72,8 @@ class LBAdjointFn(torch.autograd.Function):
             lb.adjoint_run(ctx.checkpoints)
             dth, da = lb.adjoint_grads()
         g = float(gJ)
-        dtheta = torch.from_numpy(dth[ctx.inlet] * g)
+        dtheta = torch.from_numpy(dth[ctx.inlet] * g).to(dtype=ctx.theta_meta[0],
+                                                          device=ctx.theta_meta[1])
         dalpha = torch.from_numpy(np.asarray(da) * g).to(dtype=ctx.alpha_meta[0],
                                                           device=ctx.alpha_meta[1])
         return dtheta, dalpha, None, None, None, None

@@ -1674,6 +1674,11 @@ int hemelb_lb_totals(hemelb_lb_t h, double out[4]) {
 
 static int state_io(hemelb_lb_t h, void* ext, int mode) {
     HIP_TRY(hlb::launch_state(h->layout(), h->A[h->cur], ext, h->perm, mode, h->stream), "state");
+    // a state written by the caller starts a new history: a divergence seen
+    // before it no longer applies (a fill kernel, not a memset, so that a
+    // captured graph replays it)
+    if (mode == 1 || mode == 3)
+        HIP_TRY(hlb::launch_zero_words(h->flag, 1, h->stream), "divergence flag reset");
     return HEMELB_OK;
 }
 

@@ -2,15 +2,26 @@
 //
 // The time step (paper Section 2: propagation and collision on a sparse lattice
 // of fluid sites) is one fused kernel per step: every thread owns one fluid site,
-// pulls its populations through the int32 neighbour table (a wall link names the
-// site itself with the top bit set and reads its opposite population; an iolet
-// link names a ghost slot filled just before by the ghost-fill kernel), applies
-// the LBGK collision in FP32 and stores the post-collision populations.  The work
-// is a gather/scatter stencil at ~1.3 flop per byte, bound by HBM bandwidth, so
-// there is no matrix-core work and no LDS staging.
+// pulls its populations from the upstream sites its links name, applies the LBGK
+// collision in FP32 and stores the post-collision populations.  A wall link names
+// the site itself with the top bit set and reads its opposite population; an
+// iolet link names a ghost slot.  The kernel's epilogue writes the ghost slots of
+// the next step from the freshly stored populations of the sites that own iolet
+// links, so the separate ghost-fill kernel runs only for a state that did not come
+// out of the step (after create or a restore).
+//
+// Links are found in one of three forms (see Table in kernels.hpp):
+//  * the int32 neighbour table;
+//  * the compact 16-bit table, whose codes name a slot in the tile's short list of
+//    source tiles (exchanged between lanes with ds_bpermute) and a lane;
+//  * two-level block addressing (4x4x4 blocks with fluid bitmaps): each 256-thread
+//    workgroup stages the block records its four tiles need into LDS with one
+//    coalesced load and decodes every link from LDS.
+// The work is a gather/scatter stencil at ~1.3 flop per byte, bound by HBM
+// bandwidth, so there is no matrix-core work.
 //
 // Memory layout: sites are Morton-ordered and grouped in tiles of 64, the width of
-// a wavefront.  Populations are stored [tile][direction][64] and the table
+// a wavefront.  Populations are stored [tile][direction][64] and the tables
 // [tile][direction-1][64], so one wavefront's stores of all directions and its
 // table loads each cover one contiguous block (3.75 KB and 3.5 KB for D3Q15 in
 // FP32) instead of 2Q separate address streams; every per-direction access of a
