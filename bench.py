@@ -1,12 +1,13 @@
 #!/usr/bin/env python3
 """Throughput of the sparse lattice-Boltzmann step on one MI355X.
 
-One benchmark step is one full time step of the path: the iolet ghost fill and
-the fused pull-stream + LBGK collide kernel over every fluid site of the
-workload (site updates counted as in the paper's Table 3: sites x steps / wall
-time).  Default workload: the seeded Murray tree in a 1024^3 box (root radius
-32, 7 bifurcation generations, seed 3; 5,598,432 fluid sites), D3Q15, tau 0.6,
-FP32 storage, inputs resident in HBM.  Prints one JSON line.
+One benchmark step is one full time step of the path: the fused pull-stream +
+LBGK collide kernel over every fluid site of the workload, whose epilogue also
+writes the next step's incoming iolet populations (site updates counted as in
+the paper's Table 3: sites x steps / wall time).  Default workload: the seeded
+Murray tree in a 2048^3 box (root radius 64, 8 bifurcation generations, seed 5;
+53,020,072 fluid sites), D3Q15, tau 0.6, FP32 storage, inputs resident in HBM.
+Prints one JSON line.
 """
 
 import argparse
@@ -24,6 +25,15 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11925_amd", "csrc", f)
                for f in ("kernels.hip", "kernels.hpp", "step.hpp", "lbdev.hpp", "lattice.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def method_bytes(q, storage):
+    """Bytes of one site update for the method as stated: every population read
+    once and written once, plus an int32 neighbour table entry per moving
+    direction (2 Q s + 4 (Q - 1): D3Q15 FP32 176 B, 16-bit 116 B; D3Q19 FP32
+    224 B, 16-bit 148 B)."""
+    s = 4 if storage == "f32" else 2
+    return 2 * q * s + 4 * (q - 1)
 
 
 def kernel_sha():
@@ -160,21 +170,70 @@ def pipe_errors(steps=2000):
     return out
 
 
-def cpu_baseline(geom, lattice, nsteps):
-    """The FP64 oracle as it stands, one thread, over `nsteps` full steps."""
+def cpu_baseline(geom, lattice, sites, seconds=10.0):
+    """The FP64 oracle as it stands, one thread.  With `sites` below the
+    workload's size it times the oracle's sampled step (the same arithmetic,
+    restricted to a contiguous range of `sites` sites in the middle of the site
+    list, reading the full-size state) for at least `seconds`; otherwise whole
+    steps."""
+    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle.lbgk import LBGK
+    n = geom.n_sites
     with threadpool_limits(limits=1):
-        o = LBGK(geom, lattice)
-        A = o.rest_state()
-        A, _ = o.step(A, 0)  # warm-up (first-touch allocations)
+        if sites < n:
+            a = (n - sites) // 2
+            o = LBGK(geom, lattice, sites=np.arange(a, a + sites))
+            A = np.repeat(o.lat.w[:, None], n, axis=1)
+            what = (f"oracle sampled step over {sites} contiguous sites (of {n}) of the "
+                    f"{geom.name} workload, reading the full-size FP64 state")
+        else:
+            o = LBGK(geom, lattice)
+            A = o.rest_state()
+            what = f"full oracle steps of the {geom.name} workload ({n} sites)"
+        sampled = sites < n
+        B, _ = o.step(A, 0)  # warm-up (first-touch allocations)
+        k = 0
         t0 = time.perf_counter()
-        for t in range(nsteps):
-            A, _ = o.step(A, 1 + t)
-        dt = time.perf_counter() - t0
-    return {"value": o.n * nsteps / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} full steps of the {geom.name} workload ({o.n} sites), "
-                      f"FP64 NumPy, single thread"}
+        while True:
+            B2, _ = o.step(A if sampled else B, 1 + k)
+            if not sampled:
+                B = B2
+            k += 1
+            dt = time.perf_counter() - t0
+            if dt >= seconds:
+                break
+    return {"value": o.n * k / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{k} x {what}; FP64 NumPy, single thread, {dt:.1f} s"}
+
+
+def storage_errors(make, steps):
+    """16-bit storage against FP32 storage on the benchmark's own workload and
+    lattice: both run `steps` steps from rest, then
+    max_s |x - x_f32| / max_s |x_f32| for velocity, pressure deviation and WSS.
+    (The FP32 path itself is held to the FP64 oracle by the parity tests, to
+    1e-5 in the same metric, so these figures are the 16-bit forms' error
+    against the oracle to within that.)"""
+    import numpy as np
+
+    def run(st):
+        lb = make(st)
+        lb.step(steps)
+        out = [x.cpu().numpy().astype(np.float64) for x in lb.observables()]
+        lb.close()
+        return out
+
+    def rel(a, b):
+        if a.ndim == 2:
+            return float(np.sqrt(((a - b) ** 2).sum(1)).max() / np.sqrt((b ** 2).sum(1)).max())
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    ref = run("f32")
+    out = {"steps": steps}
+    for st in ("f16", "bf16"):
+        p, u, w = run(st)
+        out[st] = {"e_u": rel(u, ref[1]), "e_p": rel(p, ref[0]), "e_wss": rel(w, ref[2])}
+    return out
 
 
 def adjoint_run(steps=4000, K=200, window=1000):
@@ -296,20 +355,42 @@ def render_run(lb, geom, size=1024, frames=20):
             "trilinear_ms_per_frame": ms_tri}
 
 
+def form_timing(make, geom, storage, steps, warmup, addressing="auto", lattice=15, obs_every=0):
+    """GLUPS (wall clock over `steps` steps) and the kernel's average duration
+    (HIP events around a second pass) of one storage/addressing/lattice form."""
+    n = geom.n_sites
+    x = make(storage, addressing, lattice)
+    d = timed_run(x, steps, warmup, obs_every)
+    km = region_kernel_ms(x, steps, 10)
+    xi = x.info()
+    x.close()
+    mb = method_bytes(lattice, storage)
+    return {"GLUPS": n * steps / d / 1e9, "ms_per_step": d / steps * 1e3, "kernel_avg_ms": km,
+            "addressing": xi["addressing_name"], "bytes_per_update": xi["bytes_per_update"],
+            "achieved_GBs": xi["bytes_per_update"] * n / (km * 1e-3) / 1e9,
+            "method_bytes_per_update": mb,
+            "frac_of_peak_method_bytes": mb * n / (km * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="tree1024")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="tree2048")
     ap.add_argument("--lattice", type=int, default=15)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for cpu_baseline (0: skip)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and adjoint runs")
+    ap.add_argument("--cpu-sites", type=int, default=2_000_000,
+                    help="sites of the oracle's sampled step for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other forms, error legs, smaller workloads and the adjoint")
+    ap.add_argument("--size-matched", action="store_true",
+                    help="also time the ~400M-site size-matched tree (tree2048_400M)")
     ap.add_argument("--obs-every", type=int, default=0,
                     help="also compute velocity/pressure/WSS every k steps inside the timed run")
     ap.add_argument("--addressing", default="auto", choices=["auto", "blocks", "table16", "table32"],
-                    help="how the kernels find upstream neighbours (auto: blocks where they apply)")
+                    help="how the kernels find upstream neighbours (auto: the library's default)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only the adjoint workload (checkpointed and recorded sweeps), one JSON line")
     ap.add_argument("--profile", action="store_true",
@@ -340,9 +421,12 @@ def main():
     n = geom.n_sites
     log(f"[bench] {n} sites ({time.perf_counter() - t0:.1f}s); creating handle")
 
-    def make(storage, addressing=args.addressing, lattice=args.lattice):
-        return LB.from_geometry(geom, lattice=lattice, storage=storage, addressing=addressing)
+    def maker(g):
+        def make(storage, addressing=args.addressing, lattice=args.lattice):
+            return LB.from_geometry(g, lattice=lattice, storage=storage, addressing=addressing)
+        return make
 
+    make = maker(geom)
     lb = make(args.storage)
     info = lb.info()
     if args.profile:
@@ -369,17 +453,21 @@ def main():
     avg_ms = region_kernel_ms(lb, args.steps, 10)
     launch_ms = kernel_avg_ms(lb, args.steps)
     bpu = info["bytes_per_update"]
-    achieved = bpu * n / (avg_ms * 1e-3) / 1e9
-    log(f"[bench] {glups:.2f} GLUPS, {ms_step:.4f} ms/step, kernel {avg_ms:.4f} ms "
-        f"-> {achieved:.0f} GB/s algorithmic")
+    mb = method_bytes(args.lattice, args.storage)
+    achieved = mb * n / (avg_ms * 1e-3) / 1e9
+    achieved_own = bpu * n / (avg_ms * 1e-3) / 1e9
+    log(f"[bench] {glups:.2f} GLUPS, {ms_step:.4f} ms/step, kernel {avg_ms:.4f} ms -> "
+        f"{achieved:.0f} GB/s at {mb} B/update ({achieved_own:.0f} GB/s at the kernel's own "
+        f"{bpu:.1f} B)")
     render = None if args.no_extra else render_run(lb, geom)
     elem = 4 if args.storage == "f32" else 2
     aux = aux_timings(lb, n, args.lattice, elem, info["bytes_per_update"])
     log(f"[bench] observables {aux['observables_ms']:.3f} ms, totals {aux['totals_ms_incl_sync']:.3f} ms")
     lb.close()
 
-    pop_bytes = 2 * args.lattice * (4 if args.storage == "f32" else 2)
+    pop_bytes = 2 * args.lattice * elem
     extra = {"bytes_per_update": bpu, "addressing": info["addressing_name"],
+             "device_GB": info["device_bytes"] / 1e9,
              "kernel_avg_ms": avg_ms,
              "kernel_avg_ms_per_launch_events": launch_ms,
              "populations_only_GBs": pop_bytes * n / (avg_ms * 1e-3) / 1e9}
@@ -401,60 +489,58 @@ def main():
     if render:
         extra["render"] = render
     extra["copy_GBs"] = copy_gbs
-    extra["frac_of_copy"] = achieved / copy_gbs
+    extra["frac_of_copy_own_bytes"] = achieved_own / copy_gbs
     del a, b
+    torch.cuda.empty_cache()
     if not args.no_extra:
+        forms = {}
         for st in ("f16", "bf16"):
-            if st == args.storage:
-                continue
-            x = make(st)
-            d = timed_run(x, args.steps, args.warmup)
-            km = region_kernel_ms(x, args.steps, 10)
-            xi = x.info()
-            xb = xi["bytes_per_update"]
-            extra[st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
-                         "addressing": xi["addressing_name"], "bytes_per_update": xb,
-                         "achieved_GBs": xb * n / (km * 1e-3) / 1e9,
-                         "speedup_vs_" + args.storage: dt / d}
-            log(f"[bench] {st}: {extra[st]['GLUPS']:.2f} GLUPS")
-            x.close()
-        if args.addressing == "auto":
-            # the addressing form the default does not pick, for comparison
-            for st in ("f32", "f16"):
-                other = "blocks" if st == "f32" else "table16"
-                x = make(st, other)
-                d = timed_run(x, args.steps, args.warmup)
-                km = region_kernel_ms(x, args.steps, 10)
-                xb = x.info()["bytes_per_update"]
-                key = f"{other}_{st}"
-                extra[key] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
-                              "bytes_per_update": xb, "achieved_GBs": xb * n / (km * 1e-3) / 1e9}
-                log(f"[bench] {other} {st}: {extra[key]['GLUPS']:.2f} GLUPS")
-                x.close()
+            if st != args.storage:
+                forms[st] = form_timing(make, geom, st, args.steps, args.warmup)
+                forms[st]["speedup_vs_" + args.storage] = ms_step / forms[st]["ms_per_step"]
+                log(f"[bench] {st}: {forms[st]['GLUPS']:.2f} GLUPS")
+        for st in ("f32", "f16"):
+            # the addressing forms the default does not pick, for comparison
+            for ad in ("blocks", "table16"):
+                key = f"{st}_{ad}"
+                forms[key] = form_timing(make, geom, st, args.steps, args.warmup, ad)
+                log(f"[bench] {key}: {forms[key]['GLUPS']:.2f} GLUPS")
         if args.lattice == 15:
             # the paper's lattice on the same workload
             for st in ("f32", "f16"):
-                x = make(st, lattice=19)
-                d = timed_run(x, args.steps, args.warmup, args.obs_every)
-                km = region_kernel_ms(x, args.steps, 10)
-                xb = x.info()["bytes_per_update"]
-                extra["d3q19_" + st] = {"GLUPS": n * args.steps / d / 1e9, "kernel_avg_ms": km,
-                                        "bytes_per_update": xb,
-                                        "addressing": x.info()["addressing_name"],
-                                        "achieved_GBs": xb * n / (km * 1e-3) / 1e9}
-                log(f"[bench] D3Q19 {st}: {extra['d3q19_' + st]['GLUPS']:.2f} GLUPS")
-                x.close()
+                key = "d3q19_" + st
+                forms[key] = form_timing(make, geom, st, args.steps, args.warmup, lattice=19,
+                                         obs_every=args.obs_every)
+                log(f"[bench] D3Q19 {st}: {forms[key]['GLUPS']:.2f} GLUPS")
+        extra["forms"] = forms
+        log("[bench] 16-bit storage errors against FP32 storage on the same workload")
+        extra["errors_16bit_vs_f32_same_workload"] = storage_errors(make, args.steps)
         log("[bench] storage errors vs oracle (pipe, 2000 steps)")
         extra["errors_vs_oracle_pipe2000"] = pipe_errors()
+        small = wl.config_geometry("tree1024")
+        mk_small = maker(small)
+        extra["tree1024"] = {"sites": small.n_sites}
+        for st in ("f32", "f16"):
+            extra["tree1024"][st] = form_timing(mk_small, small, st, args.steps, args.warmup)
+            log(f"[bench] tree1024 {st}: {extra['tree1024'][st]['GLUPS']:.2f} GLUPS")
+        del small, mk_small
+        if args.size_matched:
+            big = wl.config_geometry("tree2048_400M")
+            mk_big = maker(big)
+            extra["tree2048_400M"] = {"sites": big.n_sites}
+            for st in ("f32", "f16"):
+                extra["tree2048_400M"][st] = form_timing(mk_big, big, st, 200, 20)
+                log(f"[bench] tree2048_400M {st}: {extra['tree2048_400M'][st]['GLUPS']:.2f} GLUPS")
+            del big, mk_big
         log("[bench] adjoint workload")
         extra["adjoint"] = adjoint_run()
         log(f"[bench] adjoint: {extra['adjoint']['adjoint_GLUPS']:.3f} GLUPS (reverse incl. recompute), "
             f"{extra['adjoint']['recorded']['adjoint_GLUPS']:.3f} with every state recorded")
 
     cpu = None
-    if args.cpu_steps > 0:
-        log(f"[bench] cpu_baseline: oracle, {args.cpu_steps} steps")
-        cpu = cpu_baseline(geom, args.lattice, args.cpu_steps)
+    if args.cpu_sites > 0:
+        log(f"[bench] cpu_baseline: oracle, {args.cpu_sites} sites, >= {args.cpu_seconds} s")
+        cpu = cpu_baseline(geom, args.lattice, args.cpu_sites, args.cpu_seconds)
 
     traffic = traffic_for(args.workload, args.storage, info["addressing_name"])
     line = {
@@ -466,7 +552,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": None,
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
@@ -475,7 +561,10 @@ def main():
                    "walls": "halfway bounce-back", "addressing": info["addressing_name"],
                    "iolets": "Ladd velocity inlet + equilibrium pressure outlets"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_update": mb,
+                     "own_bytes_per_update": bpu, "achieved_own_bytes": achieved_own,
+                     "frac_own_bytes": achieved_own / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -66,9 +66,8 @@ typedef struct hemelb_lb* hemelb_lb_t;
 /* desc.flags */
 #define HEMELB_FLAG_NO_SCALE 1 /* 16-bit storage: omit the per-direction power-of-two scale */
 /* How the kernels find a site's upstream neighbours (at most one of these).  With
- * none, 16-bit storage uses block addressing where it applies and FP32 storage the
- * 16-bit table (the faster form of each on MI355X; the table falls back to int32
- * where it must):
+ * none, block addressing where it applies, else the 16-bit table (which falls back
+ * to int32 where it must):
  *   BLOCKS   two-level block addressing (the paper's decomposition of the lattice
  *            into blocks, Section 2 and Table 2): 4x4x4 blocks, each with a fluid
  *            bitmap, its first site index and the ids of its 26 neighbour blocks;

@@ -252,7 +252,7 @@ struct hemelb_lb {
     int64_t t = 0;
     bool streamed = false;
     bool ghosts_ready = false;  // A[cur]'s ghost slots hold the incoming values for time t
-    int xcd_group = 16;  // consecutive 256-site blocks per XCD (measured best at 8-16)
+    int xcd_group = 16;  // consecutive workgroups per XCD (measured best at 8-16)
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
 
@@ -949,14 +949,12 @@ int make_plan(const hemelb_lb_desc_t* d, HostPlan& P, Progress& prog) {
     for (int64_t m = 0; m < n; ++m) gbase[m + 1] += gbase[m];
     prog("iolet links");
 
-    // addressing: asked for, or by default block addressing for 16-bit storage (where
-    // it applies) and the explicit table otherwise -- the faster form of each on
-    // MI355X (with FP32 storage the table's extra bytes cost less than the block
-    // decode's longer chain of dependent loads)
+    // addressing: asked for, or by default block addressing where it applies and the
+    // explicit table otherwise (on the 53M-site tree blocks are the faster form in
+    // every storage; on the 5.6M-site tree the table is 2% faster with FP32 storage)
     bool blocks = false;
     const bool try_blocks = (d->flags & HEMELB_FLAG_BLOCKS) ||
-                            (!(d->flags & (HEMELB_FLAG_TABLE16 | HEMELB_FLAG_TABLE32)) &&
-                             d->storage != HEMELB_STORE_F32);
+                            !(d->flags & (HEMELB_FLAG_TABLE16 | HEMELB_FLAG_TABLE32));
     if (try_blocks && n > 0) {
         if (!d->coords)
             P.bp.why = "it needs site coordinates";

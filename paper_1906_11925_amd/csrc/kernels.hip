@@ -41,8 +41,8 @@ namespace hlb {
 template <int Q, int ST, bool SC, bool BRINK, bool BFL>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
-    Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha,
-    Ghosts G, int64_t t_next) {
+    Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha, Ghosts G,
+    int64_t t_next) {
     __shared__ StageLds lds;
     stream_collide_group<Q, ST, SC, BRINK, BFL>(src, dst, tb, n,
                                                 xcd_block((int32_t)blockIdx.x, xcd_group), omega,

@@ -127,8 +127,9 @@ hipError_t launch_iolet_series(const DevIolet* iolets, const double* harm, int32
 hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t t,
                              hipStream_t s);
 
-// xcd_group: consecutive blocks per XCD in the block-to-tile mapping (0: identity).
-// When ghosts_fused(), the kernel also fills dst's ghost slots for time t_next.
+// xcd_group: consecutive workgroups per XCD in the workgroup-to-tile mapping (0:
+// identity).  When ghosts_fused(), the kernel also fills dst's ghost slots for
+// time t_next.
 hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* src, void* dst,
                                  float omega, const float* alpha, int xcd_group, int64_t t_next,
                                  hipStream_t s);

@@ -235,27 +235,61 @@ struct StageLds {
     uint4 chunk[kStageChunks];
 };
 
-// Links of the sites of one 256-thread workgroup (group g = four consecutive
-// tiles) from the group's staged block records.  Every thread of the workgroup
-// calls it (it holds a barrier); `live`: the thread's wavefront has sites.
-template <int Q>
-__device__ inline void links_blocks_group(const Table& tb, int32_t g, int32_t s, bool live,
-                                          StageLds& lds, int32_t (&j)[Q]) {
-    using Lt = Lat<Q>;
-    const int32_t off = tb.grp[2 * g];
-    const int32_t cnt = tb.grp[2 * g + 1];
-    const int nown = cnt & 0xffff, nrec = cnt >> 16;
-    if (nown == 0) {  // the group's records did not fit: global records
-        if (live) links_blocks_wave<Q>(tb, s, j);
-        return;
-    }
-    const int row_chunks = (nown * kRowBytes + 15) >> 4;
+// A group's staged blob: where it starts and how many own blocks and records it
+// holds (nown = 0: the group's records did not fit and its links decode from the
+// global records).  Uniform over the workgroup.
+struct StageHdr {
+    int32_t off;
+    int nown, nrec;
+};
+
+// The group entries never change during a launch: read them through the constant
+// address space, so that they come in through the scalar cache even after the
+// kernel has stored populations (a vector load would have to wait for those
+// stores before its value could be used).
+__device__ inline StageHdr stage_header(const Table& tb, int32_t g) {
+    const __attribute__((address_space(4))) int32_t* grp =
+        (const __attribute__((address_space(4))) int32_t*)tb.grp;
+    const int32_t cnt = grp[2 * g + 1];
+    return StageHdr{grp[2 * g], cnt & 0xffff, cnt >> 16};
+}
+
+// One thread's share of staging a blob: at most one 16-byte chunk and its LDS slot
+// (-1: none).  Fetching and committing are separate so that a workgroup can load
+// the next group's blob while it works on the current one.
+struct StageChunk {
+    uint4 v;
+    int dst;
+};
+
+__device__ inline StageChunk stage_fetch(const Table& tb, const StageHdr& h) {
+    StageChunk c;
+    c.dst = -1;
+    c.v = make_uint4(0u, 0u, 0u, 0u);
+    if (h.nown == 0) return c;
+    const int row_chunks = (h.nown * kRowBytes + 15) >> 4;
     const int t = (int)threadIdx.x;
-    if (t < row_chunks)
-        lds.chunk[t] = tb.gblob[off + t];
-    else if (t < row_chunks + nrec)
-        lds.chunk[kStageRowChunks + t - row_chunks] = tb.gblob[off + t];
-    __syncthreads();
+    if (t < row_chunks + h.nrec) {
+        c.v = tb.gblob[h.off + t];
+        c.dst = t < row_chunks ? t : kStageRowChunks + t - row_chunks;
+    }
+    return c;
+}
+
+__device__ inline void stage_commit(const StageChunk& c, StageLds& lds) {
+    if (c.dst >= 0) lds.chunk[c.dst] = c.v;
+}
+
+// Links of site s from its group's staged blob in LDS (nown > 0 own blocks).  All
+// lanes of the wavefront call it (the own-block search is wave-uniform in its
+// bounds).  Per link: the row byte names the neighbour block's staged record; a
+// fluid position ranks in its mask; any other position is a wall unless the block
+// has ghost cells and the position is one (global ghost masks; rare, only next to
+// iolet planes).
+template <int Q>
+__device__ inline void decode_staged(const Table& tb, int nown, int32_t s, const StageLds& lds,
+                                     int32_t (&j)[Q]) {
+    using Lt = Lat<Q>;
     const uint8_t* rows = reinterpret_cast<const uint8_t*>(lds.chunk);
     const BlockRec* recs = reinterpret_cast<const BlockRec*>(lds.chunk + kStageRowChunks);
     // own block: the last one whose first site is at or before s (offsets ascend;
@@ -275,20 +309,17 @@ __device__ inline void links_blocks_group(const Table& tb, int32_t g, int32_t s,
     const uint8_t* row = rows + k * kRowBytes;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        // upstream point in block coordinates: neighbour block d and position pp
         const int ux = bx - Lt::cx[i], uy = by - Lt::cy[i], uz = bz - Lt::cz[i];  // in [-1, 4]
         const int d = ((ux >> 2) + 1) + 3 * ((uy >> 2) + 1) + 9 * ((uz >> 2) + 1);
         const int pp = block_pos(ux & 3, uy & 3, uz & 3);
-        const BlockRec r = recs[row[d]];  // a missing block reads the staged empty record
+        const BlockRec r = recs[row[d]];
         const uint32_t sh = (uint32_t)pp & 31u;
         const bool upper = pp >= 32;
         const uint32_t w = upper ? r.mask_hi : r.mask_lo;
         const int rank = __popc(w & ((1u << sh) - 1u)) + (upper ? __popc(r.mask_lo) : 0);
         const bool fluid = (w >> sh) & 1u;
-        int32_t v = fluid ? r.off + rank : (int32_t)0x80000000u;  // else wall...
+        int32_t v = fluid ? r.off + rank : (int32_t)0x80000000u;
         if (!fluid && r.goff >= 0) {
-            // ...unless it is a ghost cell (rare: the staged copy names the block's
-            // id; its ghost mask and first ghost index stay in global memory)
             const int32_t b2 = r.goff;
             const uint64_t gm = tb.gmask[b2];
             if ((gm >> pp) & 1ull)
@@ -296,6 +327,22 @@ __device__ inline void links_blocks_group(const Table& tb, int32_t g, int32_t s,
         }
         j[i] = v;
     }
+}
+
+// Links of the sites of one 256-thread workgroup (group g = four consecutive
+// tiles) from the group's staged block records.  Every thread of the workgroup
+// calls it (it holds a barrier); `live`: the thread's wavefront has sites.
+template <int Q>
+__device__ inline void links_blocks_group(const Table& tb, int32_t g, int32_t s, bool live,
+                                          StageLds& lds, int32_t (&j)[Q]) {
+    const StageHdr h = stage_header(tb, g);
+    if (h.nown == 0) {  // the group's records did not fit: global records
+        if (live) links_blocks_wave<Q>(tb, s, j);
+        return;
+    }
+    stage_commit(stage_fetch(tb, h), lds);
+    __syncthreads();
+    if (live) decode_staged<Q>(tb, h.nown, s, lds, j);
 }
 
 // Links of site s in a kernel whose 256-thread workgroups each cover one group g

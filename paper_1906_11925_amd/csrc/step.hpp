@@ -72,43 +72,59 @@ __device__ inline float ghost_value(const Ghosts& G, int64_t l, int i, const flo
 #define HLB_FUSE_GHOSTS 1
 #endif
 
-// Pull, collide and store one site whose links are decoded in j.
-template <int Q, int ST, bool SC, bool BRINK, bool BFL>
-__device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
-                                   typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
-                                   const float* __restrict__ alpha, const Ghosts& G,
-                                   int64_t t_next, int32_t s, const int32_t (&j)[Q]) {
-    using C = Codec<Q, ST, SC>;
+// The pulled (pre-collision) deviations of one site and what the epilogue needs
+// about its iolet links.
+template <int Q>
+struct Pulled {
     float d[Q];
-    d[0] = C::dec(0, src[tix<Q>(0, s)]);
+    uint32_t gmask;  // directions of the site's iolet links (fused ghost epilogue)
+    int64_t gl;      // the first of those links
+};
+
+// Pull the populations of site s whose links are decoded in j.
+template <int Q, int ST, bool SC, bool BFL>
+__device__ inline void site_pull(const typename Store<ST>::T* __restrict__ src, int32_t n,
+                                 const Ghosts& G, int32_t s, const int32_t (&j)[Q], Pulled<Q>& P) {
+    using C = Codec<Q, ST, SC>;
+    P.d[0] = C::dec(0, src[tix<Q>(0, s)]);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         int dir;
         int32_t site;
         link_src(i, j[i], s, dir, site);
-        d[i] = C::dec(i, src[tix<Q>(dir, site)]);
+        P.d[i] = C::dec(i, src[tix<Q>(dir, site)]);
     }
-    if constexpr (BFL) apply_bfl<Q, ST, SC>(src, s, n, j, d);
+    if constexpr (BFL) apply_bfl<Q, ST, SC>(src, s, n, j, P.d);
+    P.gmask = 0;
+    P.gl = -1;
 #if HLB_FUSE_GHOSTS
     // directions of the site's iolet links and the first of those links (they are
     // consecutive in the link list, in direction order), for the epilogue
-    uint32_t gmask = 0;
-    int64_t gl = -1;
-    {
-        int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
+    int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
 #pragma unroll
-        for (int i = 2; i < Q; ++i) top = max(top, j[i]);
-        if (top >= n) {
+    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+    if (top >= n) {
 #pragma unroll
-            for (int i = 1; i < Q; ++i)
-                if (j[i] >= n) {
-                    if (gl < 0) gl = ghost_link<Q>(G, n, j[i], i);
-                    gmask |= 1u << i;
-                }
-        }
+        for (int i = 1; i < Q; ++i)
+            if (j[i] >= n) {
+                if (P.gl < 0) P.gl = ghost_link<Q>(G, n, j[i], i);
+                P.gmask |= 1u << i;
+            }
     }
+#else
+    (void)G;
 #endif
+}
 
+// Collide the pulled populations of site s and store them (and, with the fused
+// ghost epilogue, the incoming populations of its iolet links for time t_next).
+template <int Q, int ST, bool SC, bool BRINK>
+__device__ inline void site_collide_store(typename Store<ST>::T* __restrict__ dst, int32_t n,
+                                          float omega, const float* __restrict__ alpha,
+                                          const Ghosts& G, int64_t t_next, int32_t s,
+                                          const Pulled<Q>& P) {
+    using C = Codec<Q, ST, SC>;
+    const float(&d)[Q] = P.d;
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
     const float rho = 1.0f + drho;
@@ -133,11 +149,12 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
     // The iolet links of a site are consecutive in the link list, in direction
     // order.  With one slot per link (table encodings) the first one is the
     // smallest ghost slot the site pulls from; with shared ghost cells (block
-    // addressing) it is found by a binary search of the list.
-    if (gmask) {
+    // addressing) it is found through the cell's link list.
+    if (P.gmask) {
+        int64_t gl = P.gl;
 #pragma unroll
         for (int i = 1; i < Q; ++i)
-            if (gmask & (1u << i)) {
+            if (P.gmask & (1u << i)) {
                 dst[tix<Q>(i, ghost_slot(G, n, gl))] = C::enc(i, ghost_value<Q>(G, gl, i, vs, t_next));
                 ++gl;
             }
@@ -146,7 +163,19 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
     (void)vs;
     (void)G;
     (void)t_next;
+    (void)n;
 #endif
+}
+
+// Pull, collide and store one site whose links are decoded in j.
+template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+__device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
+                                   typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
+                                   const float* __restrict__ alpha, const Ghosts& G,
+                                   int64_t t_next, int32_t s, const int32_t (&j)[Q]) {
+    Pulled<Q> P;
+    site_pull<Q, ST, SC, BFL>(src, n, G, s, j, P);
+    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P);
 }
 
 // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With

@@ -12,6 +12,9 @@ and its FP32-adjoint / FP64-accumulated gradients are compared with it:
 * the autograd.Function returns the same gradients.
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -352,3 +355,77 @@ def test_recorded_sweep_is_bit_identical_on_the_pulsatile_aneurysm():
         lb.close()
     for x, y in zip(*out):
         assert np.array_equal(x, y)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "adjoint_aneurysm_half.json")
+
+
+@pytest.mark.timeout(900)
+def test_aneurysm_half_live_inlet_gradient():
+    """The adjoint workload's geometry from rest, long enough for the inlet's signal
+    to reach the dome and the outlet: 600 steps, objective window = the last 200,
+    checkpoints every 100 (the paired sweep).  The objective's constants (Q*, the
+    shear weight) and central finite differences of J with respect to the three
+    inlet coefficients come from the FP64 oracle (tests/golden/
+    make_adjoint_aneurysm_half.py).  The GPU's gradient with respect to the inlet
+    coefficients must be non-zero and agree with those finite differences and
+    with the oracle's adjoint to 1e-4; the Brinkman-field gradient and dJ/dA_0
+    agree with the oracle's adjoint to 1e-4."""
+    _gpu()
+    with open(GOLDEN) as f:
+        rec = json.load(f)
+    g = wl.aneurysm(half=True)
+    n = g.n_sites
+    T, W = rec["T"], tuple(rec["window"])
+    alpha = np.random.default_rng(4).uniform(0.0, 0.01, n).astype(np.float32).astype(np.float64)
+    c = g.coords.astype(np.float64)
+    C, R = g.info["centre"], g.info["radius"]
+    sphere = ((c[:, 0] - C[0]) ** 2 + (c[:, 1] - C[1]) ** 2 + (c[:, 2] - C[2]) ** 2) < (R + 2) ** 2
+    o = LBGK(g, 15, alpha=alpha)
+    _, has = o.wall_normals()
+    obj = Objective(1, rec["q_target"], has & sphere, rec["lam"], W)
+    adj = Adjoint(o, obj)
+    J_ref, tape, q_ref = adj.forward(o.rest_state(), T)
+    assert abs(J_ref - rec["J"]) <= 1e-9 * abs(rec["J"])
+    theta_ref, ahat_ref, g0_ref = adj.backward(tape, T)
+    del tape
+    P = dict(g=g, obj=obj, alpha=alpha, T=T, lattice=15, d0=None)
+    (J, _, _), q, th, da, g0 = _gpu_run(P, 100, pipelined=True)
+    fd = np.asarray(rec["dJ_dtheta_fd"])
+    e_fd = _rel(th, fd)
+    e_th, e_a, e_g = _rel(th, theta_ref[0]), _rel(da, ahat_ref), _rel(g0, g0_ref)
+    print(f"aneurysm_half T={T}: J={J:.6e} (rel {abs(J - J_ref) / J_ref:.2e}) dJ/dtheta={th} "
+          f"fd={fd} e_fd={e_fd:.2e} e_theta={e_th:.2e} e_alpha={e_a:.2e} e_A0={e_g:.2e}",
+          flush=True)
+    assert np.abs(th).max() > 0 and np.abs(fd).max() > 0
+    assert abs(J - J_ref) <= 1e-5 * abs(J_ref) and _rel(q, q_ref) <= 1e-5
+    assert e_fd <= 1e-4 and e_th <= 1e-4 and e_a <= 1e-4 and e_g <= 1e-4
+
+
+def test_autograd_meta_and_no_record_without_grad(tiny):
+    """The autograd function returns dtheta in theta's dtype and device, and a
+    forward that needs no gradient keeps no record of the trajectory."""
+    _gpu()
+    g, obj = tiny["g"], tiny["obj"]
+    io = g.iolets[0]
+    lb = LB.from_geometry(g, alpha=tiny["alpha"].astype(np.float32))
+    lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
+    theta = torch.tensor([io.mean, *io.cos, *io.sin], dtype=torch.float32, device="cuda")
+    alpha = torch.tensor(tiny["alpha"], dtype=torch.float32, device="cuda")
+    with torch.no_grad():
+        LBAdjointFn.apply(theta, alpha, lb, 0, tiny["T"], 0)
+    # the first run sizes the iolet-value table; a record would add T + 1 states
+    base = lb.info()["device_bytes"]
+    with torch.no_grad():
+        J0 = LBAdjointFn.apply(theta, alpha, lb, 0, tiny["T"], 0)
+    assert lb.info()["device_bytes"] == base
+    theta.requires_grad_(True)
+    J = LBAdjointFn.apply(theta, alpha, lb, 0, tiny["T"], 0)
+    assert J.item() == J0.item()
+    J.backward()
+    assert theta.grad.dtype == torch.float32 and theta.grad.is_cuda
+    assert lb.info()["device_bytes"] == base
+    ref = _gpu_run(tiny, 9)[2]
+    assert np.allclose(theta.grad.cpu().numpy(), ref, rtol=1e-6, atol=0)
+    lb.close()

@@ -540,16 +540,16 @@ def test_addressing_modes_are_bit_identical(name, q, storage):
 
 
 def test_auto_addressing_prefers_blocks_and_falls_back():
-    """The default is block addressing for 16-bit storage (with coordinates and
-    halfway walls) and the 16-bit table for FP32; a periodic lattice (links that
-    wrap) and interpolated walls use the table; asking for blocks where they do not
-    apply is an error that names the reason."""
+    """The default is block addressing (with coordinates and halfway walls) in
+    every storage; a periodic lattice (links that wrap) and interpolated walls use
+    the table; asking for blocks where they do not apply is an error that names
+    the reason."""
     _gpu()
     lb = LB.from_geometry(wl.pipe(), storage="f16")
     assert lb.info()["addressing"] == L.ADDR_BLOCKS
     lb.close()
     lb = LB.from_geometry(wl.pipe())
-    assert lb.info()["addressing"] == L.ADDR_TABLE16
+    assert lb.info()["addressing"] == L.ADDR_BLOCKS
     lb.close()
     per = wl.periodic_box(5, 7, 6)
     lb = LB.from_geometry(per, storage="f16")

@@ -41,15 +41,15 @@ def big():
     return g, coords, nbr
 
 
-@pytest.mark.parametrize("storage,addressing", [("f32", L.ADDR_TABLE16), ("f16", L.ADDR_BLOCKS)],
+@pytest.mark.parametrize("storage,addressing", [("f32", "table16"), ("f16", "blocks")],
                          ids=["f32-table16", "f16-blocks"])
 def test_streaming_is_the_link_permutation_at_400M_sites(big, storage, addressing):
     g, coords, nbr = big
     n, q = g.n_sites, 15
     assert q * n > 2 ** 31
     lb = LB(nbr, math.inf, lattice=q, storage=storage, coords=coords, iolets=list(g.iolets),
-            site_weight=g.site_weight())
-    assert lb.info()["addressing"] == addressing
+            site_weight=g.site_weight(), addressing=addressing)
+    assert lb.info()["addressing"] == {"table16": L.ADDR_TABLE16, "blocks": L.ADDR_BLOCKS}[addressing]
     gen = torch.Generator(device="cuda").manual_seed(23)
     d = torch.rand((q, n), generator=gen, device="cuda")
     d.sub_(0.5).mul_(2e-3)

@@ -74,14 +74,15 @@ def test_block_addressing_is_chosen_and_sized(name, q):
     assert auto["device_bytes"] < t16["device_bytes"] < t32["device_bytes"]
 
 
-def test_default_addressing_follows_the_storage():
-    """Without a request: block addressing for 16-bit storage, the 16-bit table for
-    FP32 storage."""
+def test_default_addressing_is_blocks_where_they_apply():
+    """Without a request: block addressing in every storage when the links are the
+    ones the positions imply; the 16-bit table without coordinates."""
     g = wl.pipe()
-    _, nbr, kw = _args(g)
-    assert plan(nbr, g.tau, **kw)["addressing"] == L.ADDR_TABLE16
-    for st in ("f16", "bf16"):
+    coords, nbr, kw = _args(g)
+    for st in ("f32", "f16", "bf16"):
         assert plan(nbr, g.tau, storage=st, **kw)["addressing"] == L.ADDR_BLOCKS
+    kw.pop("coords")
+    assert plan(nbr, g.tau, **kw)["addressing"] == L.ADDR_TABLE16
 
 
 def test_plan_matches_population_bytes():
