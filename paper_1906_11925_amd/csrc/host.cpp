@@ -253,6 +253,11 @@ struct hemelb_lb {
     bool streamed = false;
     bool ghosts_ready = false;  // A[cur]'s ghost slots hold the incoming values for time t
     int xcd_group = 16;  // consecutive workgroups per XCD (measured best at 8-16)
+    // stream-collide workgroups that copy their own tiles' populations into LDS
+    // (block addressing only): 8 tiles with FP32 storage (the tile rows are two
+    // cache lines, and the copy keeps the in-group pulls off the L1), none with
+    // 16-bit storage (slower there)
+    int stage_tiles = 0;
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
 
@@ -329,7 +334,7 @@ struct hemelb_lb {
                            hlb::Table{tbl, t16, toff, tlist, brec, gmask, bnbr, tblock,
                                       reinterpret_cast<const uint4*>(gblob), grp, nfluid, nblocks,
                                       (int32_t)n},
-                           bfl};
+                           bfl, stage_tiles};
     }
     hlb::Ghosts ghosts() const {
         return hlb::Ghosts{nghost,  g_slot,   g_cell_link, g_site,  g_dir,   g_iolet,
@@ -1467,6 +1472,11 @@ static int init_handle(hemelb_lb* h, hemelb_lb_t* out, const hemelb_lb_desc_t* d
     h->omega = std::isinf(d->tau) ? 0.0f : (float)(1.0 / d->tau);
     h->stream = static_cast<hipStream_t>(d->stream);
     if (const char* e = getenv("HEMELB_XCD_GROUP")) h->xcd_group = std::max(0, atoi(e));
+    h->stage_tiles = h->storage == HEMELB_STORE_F32 ? 8 : 0;
+    if (const char* e = getenv("HEMELB_STAGE_TILES")) {
+        const int v = atoi(e);
+        h->stage_tiles = (v == 4 || v == 8 || v == 16) ? v : 0;
+    }
     (void)hipGetDevice(&h->device);
     const int q = h->q;
     const int64_t n = h->n;

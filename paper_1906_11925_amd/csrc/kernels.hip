@@ -49,6 +49,19 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
                                                 alpha, G, t_next, lds);
 }
 
+// workgroups of W tiles with their own populations staged in LDS (block addressing)
+template <int Q, int ST, bool SC, bool BRINK, int W>
+__global__ __launch_bounds__(W * kTile) void k_stream_collide_staged(
+    const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
+    Table tb, int32_t n, int32_t tiles_alloc, int32_t xcd_group, float omega,
+    const float* __restrict__ alpha, Ghosts G, int64_t t_next) {
+    __shared__ typename Store<ST>::T pops[W][Q][kTile];
+    __shared__ StageLds lds[W / 4];
+    const int32_t w = xcd_block((int32_t)blockIdx.x, xcd_group);
+    stream_collide_staged<Q, ST, SC, BRINK, W>(src, dst, tb, n, tiles_alloc, w * W, omega, alpha,
+                                               G, t_next, pops, lds);
+}
+
 // ---------------------------------------------------------------------------
 // iolet ghost fill: the incoming population of every iolet link for this step
 // ---------------------------------------------------------------------------
@@ -295,10 +308,41 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
     });
 }
 
+template <int W>
+static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* src, void* dst,
+                                float omega, const float* alpha, int xcd_group, int64_t t_next,
+                                hipStream_t s) {
+    const int64_t tiles = (L.n + kTile - 1) / kTile;
+    const int64_t nb = (tiles + W - 1) / W;
+    // the same number of tiles per XCD chunk as the four-tile workgroups
+    const int32_t per = xcd_group > 0 ? std::max(1, xcd_group * 4 / W) : 0;
+    int64_t grid = nb;
+    if (per > 0) grid = ((nb + 8 * per - 1) / (8 * per)) * (8 * per);
+    const int32_t tiles_alloc = (int32_t)(L.slots / kTile);
+    return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
+        using Tg = decltype(tag);
+        using T = typename Store<Tg::ST>::T;
+        if (alpha)
+            k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W><<<(unsigned)grid, W * kTile, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, tiles_alloc,
+                per, omega, alpha, G, t_next);
+        else
+            k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W><<<(unsigned)grid, W * kTile, 0, s>>>(
+                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, tiles_alloc,
+                per, omega, nullptr, G, t_next);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* src, void* dst,
                                  float omega, const float* alpha, int xcd_group, int64_t t_next,
                                  hipStream_t s) {
     if (L.n == 0) return hipSuccess;
+    if (L.stage_tiles > 0 && L.tb.grp && !L.bfl) {
+        if (L.stage_tiles == 4) return launch_staged<4>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
+        if (L.stage_tiles == 8) return launch_staged<8>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
+        if (L.stage_tiles == 16) return launch_staged<16>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
+    }
     int64_t nb = (L.n + kScBlock - 1) / kScBlock;
     const int32_t per = xcd_group > 0 ? xcd_group : 0;
     int64_t grid = nb;

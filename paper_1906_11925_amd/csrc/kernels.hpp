@@ -92,6 +92,9 @@ struct Layout {
     int64_t slots;  // site + ghost slots per direction, a multiple of 64
     Table tb;
     bool bfl;       // some wall links carry an interpolated-wall fraction
+    // with block addressing and halfway walls: workgroups of this many tiles (4, 8
+    // or 16) copy their own populations into LDS first (0: four tiles, no copy)
+    int stage_tiles;
 };
 
 // Iolet links, sorted by site then direction.  Link l's incoming population lives

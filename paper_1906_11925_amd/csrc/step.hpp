@@ -208,4 +208,94 @@ __device__ inline void stream_collide_group(const typename Store<ST>::T* __restr
     site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j);
 }
 
+// Links of the sites of a workgroup of W tiles (W a multiple of 4) from the
+// staged records of its W/4 groups: every thread takes its share of its group's
+// blob, one barrier, then every wavefront decodes its tile.  Groups whose records
+// did not fit decode from the global records.  Every thread calls it.
+template <int Q, int W>
+__device__ inline void links_tiles(const Table& tb, int32_t T0, int32_t n, StageLds (&lds)[W / 4],
+                                   int32_t (&j)[Q]) {
+    const int wave = (int)threadIdx.x >> kTileShift;
+    const int32_t g = (T0 >> 2) + (wave >> 2);  // this thread's group of four tiles
+    const int32_t s = (T0 << kTileShift) + (int32_t)threadIdx.x;
+    const bool live = (s & ~(kTile - 1)) < n;
+    StageHdr h{0, 0, 0};
+    if (((int64_t)g << 8) < n) {
+        h = stage_header(tb, g);
+        // the group's 256 threads fetch its blob (thread index within the group)
+        const int32_t t = (int32_t)threadIdx.x & (kScBlock - 1);
+        if (h.nown > 0) {
+            const int row_chunks = (h.nown * kRowBytes + 15) >> 4;
+            if (t < row_chunks + h.nrec)
+                lds[wave >> 2].chunk[t < row_chunks ? t : kStageRowChunks + t - row_chunks] =
+                    tb.gblob[h.off + t];
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+    if (h.nown > 0)
+        decode_staged<Q>(tb, h.nown, s, lds[wave >> 2], j);
+    else
+        links_blocks_wave<Q>(tb, s, j);
+}
+
+// The fused step for a workgroup of W consecutive tiles (64 W threads) that first
+// copies its own tiles' populations into LDS with coalesced loads: a link whose
+// upstream site (or ghost slot) lies in those tiles reads LDS, any other reads
+// global memory, so each wavefront's gathers touch only the lines of tiles outside
+// the workgroup.  Block addressing, halfway walls.  Every thread calls it.
+template <int Q, int ST, bool SC, bool BRINK, int W>
+__device__ inline void stream_collide_staged(const typename Store<ST>::T* __restrict__ src,
+                                             typename Store<ST>::T* __restrict__ dst,
+                                             const Table& tb, int32_t n, int32_t tiles_alloc,
+                                             int32_t T0, float omega,
+                                             const float* __restrict__ alpha, const Ghosts& G,
+                                             int64_t t_next,
+                                             typename Store<ST>::T (&pops)[W][Q][kTile],
+                                             StageLds (&lds)[W / 4]) {
+    using T = typename Store<ST>::T;
+    using C = Codec<Q, ST, SC>;
+    if (((int64_t)T0 << kTileShift) >= n) return;
+    const int wave = (int)threadIdx.x >> kTileShift, lane = (int)threadIdx.x & (kTile - 1);
+    const int32_t staged = min(W, tiles_alloc - T0);  // tiles of the array in this workgroup
+    if (wave < staged) {
+        const int32_t s = ((T0 + wave) << kTileShift) + lane;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) pops[wave][i][lane] = src[tix<Q>(i, s)];
+    }
+    int32_t j[Q];
+    links_tiles<Q, W>(tb, T0, n, lds, j);  // holds the barrier after the staging
+    const int32_t s = (T0 << kTileShift) + (int32_t)threadIdx.x;
+    if (s >= n) return;
+    const int32_t lo = T0 << kTileShift;
+    const uint32_t span = (uint32_t)staged << kTileShift;
+    Pulled<Q> P;
+    P.d[0] = C::dec(0, pops[wave][0][lane]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        int dir;
+        int32_t site;
+        link_src(i, j[i], s, dir, site);
+        const uint32_t r = (uint32_t)(site - lo);
+        const T v = r < span ? pops[r >> kTileShift][dir][r & (kTile - 1)] : src[tix<Q>(dir, site)];
+        P.d[i] = C::dec(i, v);
+    }
+    P.gmask = 0;
+    P.gl = -1;
+#if HLB_FUSE_GHOSTS
+    int32_t top = j[1];
+#pragma unroll
+    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
+    if (top >= n) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+            if (j[i] >= n) {
+                if (P.gl < 0) P.gl = ghost_link<Q>(G, n, j[i], i);
+                P.gmask |= 1u << i;
+            }
+    }
+#endif
+    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P);
+}
+
 }  // namespace hlb
