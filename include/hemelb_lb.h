@@ -261,6 +261,20 @@ int hemelb_lb_observables(hemelb_lb_t h, float* p, float* u, float* wss);
 int hemelb_lb_totals(hemelb_lb_t h, double out[4]);
 
 /*
+ * hemelb_lb_totals for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FP64 totals, bit for bit, written to device memory `out` (double[4], caller-owned)
+ * asynchronously on the handle's stream, with no synchronisation and no allocation.
+ * The reduction's partial sums live in a static device array of 1024 x 4 doubles,
+ * one per GPU, held until the process ends; the first call on a GPU looks up its
+ * address.  Every call on a GPU shares that array: calls that overlap on one GPU
+ * (other streams or threads) race and their results are undefined.  Any lattice
+ * size fits (the reduction uses at most 1024 blocks); EINVAL otherwise.  A
+ * non-finite state shows as non-finite totals; the divergence flag is not touched.
+ */
+int hemelb_lb_totals_noalloc(hemelb_lb_t h, double* out);
+
+/*
  * Stored populations in the storage format (checkpoint / resume):
  *   dst/src  device, [lattice][N] in caller order; element type float (F32) or
  *            16-bit (F16/BF16); value = (f_i - w_i) * scale_i, where scale_i is a

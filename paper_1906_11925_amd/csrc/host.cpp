@@ -1680,6 +1680,16 @@ int hemelb_lb_totals(hemelb_lb_t h, double out[4]) {
     return HEMELB_OK;
 }
 
+int hemelb_lb_totals_noalloc(hemelb_lb_t h, double* out) {
+    if (!h || !out) return fail(HEMELB_EINVAL, "NULL argument");
+    if (hlb::totals_parts(h->n) > hlb::totals_scratch_parts())
+        return fail(HEMELB_EINVAL, "%lld reduction blocks exceed the scratch of %lld",
+                    (long long)hlb::totals_parts(h->n), (long long)hlb::totals_scratch_parts());
+    HIP_TRY(hipSetDevice(h->device), "set device");
+    HIP_TRY(hlb::launch_totals_noalloc(h->layout(), h->A[h->cur], out, h->stream), "totals");
+    return HEMELB_OK;
+}
+
 static int state_io(hemelb_lb_t h, void* ext, int mode) {
     HIP_TRY(hlb::launch_state(h->layout(), h->A[h->cur], ext, h->perm, mode, h->stream), "state");
     // a state written by the caller starts a new history: a divergence seen

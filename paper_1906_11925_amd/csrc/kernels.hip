@@ -30,6 +30,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "lattice.hpp"
@@ -391,6 +392,47 @@ hipError_t launch_totals(const Layout& L, const void* A, double* partial, int64_
     if (e != hipSuccess) return e;
     k_totals_final<<<1, kBlock, 0, s>>>(partial, (int32_t)nparts, (double)L.n, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// totals without any allocation: the reduction's partial sums live in a
+// file-scope device array, one copy per GPU
+// ---------------------------------------------------------------------------
+constexpr int kScratchDoubles = kTotBlocks * 4 + 2;  // partial sums, then the flag word
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each GPU
+
+// The device address of this GPU's `scratch` (the host-side name is only a
+// stand-in), looked up once per device with that device current.
+static hipError_t scratch_address(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int64_t totals_scratch_parts() { return kTotBlocks; }
+
+hipError_t launch_totals_noalloc(const Layout& L, const void* A, double* out, hipStream_t s) {
+    const int64_t nparts = totals_parts(L.n);
+    if (nparts > kTotBlocks) return hipErrorInvalidValue;
+    double* sp = nullptr;
+    hipError_t e = scratch_address(&sp);
+    if (e != hipSuccess) return e;
+    int32_t* flag = reinterpret_cast<int32_t*>(sp + (int64_t)kTotBlocks * 4);
+    return launch_totals(L, A, sp, nparts, out, flag, s);
 }
 
 hipError_t launch_state(const Layout& L, void* A, void* ext, const int32_t* perm, int mode,

@@ -149,6 +149,12 @@ hipError_t launch_totals(const Layout& L, const void* A, double* partial, int64_
                          double* out, int32_t* flag, hipStream_t s);
 int64_t totals_parts(int64_t n);
 
+// The same totals with the partial sums in a per-GPU static scratch array of
+// totals_scratch_parts() blocks (no allocation, no synchronisation); `out` is a
+// device double[4].  Calls that overlap on one GPU share the array.
+hipError_t launch_totals_noalloc(const Layout& L, const void* A, double* out, hipStream_t s);
+int64_t totals_scratch_parts();
+
 // mode 0: raw get, 1: raw set, 2: decoded get (float), 3: decoded set (float)
 hipError_t launch_state(const Layout& L, void* A, void* ext, const int32_t* perm, int mode,
                         hipStream_t s);

@@ -93,6 +93,7 @@ _SIGS = {
     "hemelb_lb_set_stream": (c_int32, [c_void_p, c_void_p]),
     "hemelb_lb_observables": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "hemelb_lb_totals": (c_int32, [c_void_p, P(c_double)]),
+    "hemelb_lb_totals_noalloc": (c_int32, [c_void_p, c_void_p]),
     "hemelb_lb_get_state": (c_int32, [c_void_p, c_void_p, P(c_int64)]),
     "hemelb_lb_set_state": (c_int32, [c_void_p, c_void_p, c_int64]),
     "hemelb_lb_get_deviations": (c_int32, [c_void_p, c_void_p]),

@@ -32,6 +32,10 @@ int64_t totals_parts(int64_t n) {
     const int64_t nb = (n + kBlock - 1) / kBlock;
     return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
 }
+hipError_t launch_totals_noalloc(const Layout&, const void*, double*, hipStream_t) {
+    return hipErrorNoDevice;
+}
+int64_t totals_scratch_parts() { return 1024; }
 hipError_t launch_state(const Layout&, void*, void*, const int32_t*, int, hipStream_t) {
     return hipErrorNoDevice;
 }
