@@ -5,28 +5,28 @@
 //   J = sum_{t in W} (Q(t) - Q*)^2 + lam * mean_{t in W} mean_{s in D} WSS_s(f_t),
 //   Q(t) = sum over the outlet's iolet links (s, i) of A_t[opp(i)][s] - f_t[i][s].
 //
-// One reverse step t (given g = dJ/dA_{t+1}, FP32, same tiled layout as the
-// populations) is one kernel, k_adj_scatter, one thread per site:
-//  * it re-gathers f_t from the taped A_t, applies the transposed collision
-//    Jacobian
-//      fhat_j = (1 - omega) g_j + omega (a + c_j . b),
-//      a = sum_i g_i dfeq_i/drho, b = sum_i g_i dfeq_i/dm  (Brinkman-aware),
-//    adds the wall-shear objective term, accumulates dJ/dalpha_s in FP64, and
-//    writes fhat_i to exactly the address the forward pull read f_i from (the
-//    upstream site or the site's own opposite population for a wall link).  Every
-//    population location is read by at most one link, so the push needs no
-//    atomics; the populations that leave through iolets are read by nobody and
-//    are set to zero here.
+// The reverse sweep runs in pull form, one thread per site, and each kernel writes
+// only the rows of its own sites:
+//  * the stream transpose: population k of site s was read in the forward by the
+//    link opp(k) of s pulling the other way (from the site s + c_k), by s itself
+//    across a wall (bounce-back), or, across an iolet, by nobody; so
+//    dJ/dA_t[k][s] gathers fhat_t = dJ/df_t along the site's own decoded links,
+//    with the direction reversed.  The forward's table validation guarantees that
+//    links pair up this way.
 //  * at a site with iolet links the same thread turns the adjoints of the values
 //    those links pulled (the incoming iolet populations) into their sources: the
 //    Ladd term sends its adjoint to the site's opposite population and (times its
 //    coefficient and the tabulated Fourier basis) to the inlet coefficients; the
 //    pressure equilibrium sends it to all of the site's own populations through
-//    u(A_t[:, s]); the outlet flux term of the objective enters here too.  What
-//    goes to the site's own populations of A_t is held in a per-site pending
-//    buffer and added when the site reads them in the next (earlier) reverse
-//    step, after every push of this step has landed; k_adj_flush adds what is
-//    left at the end of a segment.
+//    u(A_t[:, s]); the outlet flux term of the objective enters here too.
+//  * the transposed collision Jacobian at the taped state of the previous step,
+//      fhat_j = (1 - omega) g_j + omega (a + c_j . b),
+//      a = sum_i g_i dfeq_i/drho, b = sum_i g_i dfeq_i/dm  (Brinkman-aware),
+//    plus the wall-shear objective term, and dJ/dalpha_s accumulated in FP64.
+// The first two are the transpose of step t + 1 and the third that of step t, so one
+// kernel covers parts of two steps: fhat_{t+1} -> fhat_t.  A segment starts from
+// ghat (its first kernel skips the gather) and ends with a kernel that applies the
+// stream transpose alone, so the sweep holds dJ/dA_t between segments.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -174,13 +174,16 @@ __global__ __launch_bounds__(64) void k_objective_final(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// reverse step at iolet sites (called by the site's own thread)
+// iolet terms of the stream transpose (called by the site's own thread)
 // ---------------------------------------------------------------------------
+// Adds to g the adjoint that the values pulled by the iolet links of site s (at
+// the step whose ghosts were filled from A) send to the site's own populations of
+// A, and accumulates the inlet-coefficient adjoints.  fh: dJ/df of that step.
 template <int Q, int ST, bool SC>
-__device__ inline void iolet_adjoint(const typename Store<ST>::T* __restrict__ A, int32_t s,
-                                           const int32_t (&j)[Q], const float (&fh)[Q],
-                                           const Ghosts& G, const IoletAdj& I, int64_t kis,
-                                           int32_t n) {
+__device__ inline void iolet_terms(const typename Store<ST>::T* __restrict__ A, int32_t s,
+                                   const int32_t (&j)[Q], const float* __restrict__ fh,
+                                   const Ghosts& G, const IoletAdj& I, int64_t kis, int32_t n,
+                                   float (&g)[Q]) {
     using C = Codec<Q, ST, SC>;
     using Lt = Lat<Q>;
     float d[Q];
@@ -204,7 +207,7 @@ __device__ inline void iolet_adjoint(const typename Store<ST>::T* __restrict__ A
         const int kio = G.iolet[l];
         const DevIolet io = G.iolets[kio];
         const int64_t step = ((int64_t)I.t - G.vals_t0) * G.n_iolets + kio;
-        float gh = fh[i];  // adjoint of the incoming value the link pulled
+        float gh = fh[tix<Q>(i, s)];  // adjoint of the incoming value the link pulled
         if (kio == I.outlet && I.q_index >= 0) {
             gh -= (float)qbar;
             acc[o] += (float)qbar;
@@ -236,89 +239,101 @@ __device__ inline void iolet_adjoint(const typename Store<ST>::T* __restrict__ A
         ++l;
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) I.pend[kis * Q + i] = acc[i];
+    for (int i = 0; i < Q; ++i) g[i] += acc[i];
 }
 
 // ---------------------------------------------------------------------------
-// reverse step: transposed collision + push along the forward's pull addresses
+// one reverse kernel (group grp of four tiles; every thread of the workgroup
+// calls it).  A: taped state of the collision step (ADJ_OWN, ADJ_PULL); Ai: taped
+// state of the stream step (ADJ_PULL, ADJ_FINAL).
 // ---------------------------------------------------------------------------
-// The reverse step of one workgroup (group grp of four tiles).  Every thread of
-// the workgroup calls it.
-template <int Q, int ST, bool SC, bool BRINK>
-__device__ inline void adj_scatter_group(
-    const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
-    float* __restrict__ gout, const Table& tb, int32_t n, float omega,
-    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
+template <int Q, int ST, bool SC, bool BRINK, int MODE>
+__device__ inline void adj_group(
+    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ Ai,
+    const float* __restrict__ gin, float* __restrict__ gout, const Table& tb, int32_t n,
+    float omega, const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal, const Ghosts& G,
     const IoletAdj& I, int32_t grp, StageLds& lds) {
     using Lt = Lat<Q>;
     static_assert(kBlock == 4 * kTile, "a workgroup covers one group of four tiles");
+    if ((int64_t)grp * kBlock >= n) return;  // the whole workgroup lies past the end
     const int32_t s = grp * kBlock + threadIdx.x;
     const bool live = (s & ~(kTile - 1)) < n;
     const bool mine = live && s < n;
-    // the incoming adjoints and per-site inputs do not depend on the links: issue
-    // their loads before the link decode so the two latencies overlap
     float g[Q];
+    // per-site inputs that do not depend on the links: issue their loads before the
+    // link decode so the two latencies overlap
+    if constexpr (MODE == ADJ_OWN) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = mine ? gin[tix<Q>(i, s)] : 0.f;
-    const float keep = BRINK && mine ? 1.0f - alpha[s] : 1.0f;
-    const float ws = wss_w && mine ? wss_w[s] : 0.f;
-    float d[Q];
+        for (int i = 0; i < Q; ++i) g[i] = mine ? gin[tix<Q>(i, s)] : 0.f;
+    }
+    const float keep = BRINK && mine && MODE != ADJ_FINAL ? 1.0f - alpha[s] : 1.0f;
+    const float ws = wss_w && mine && MODE != ADJ_FINAL ? wss_w[s] : 0.f;
     int32_t j[Q];
     links_group<Q, false>(tb, grp, s, live, lds, j);
     if (!mine) return;
-    gather_pre<Q, ST, SC>(A, s, n, d, j);
-    // a site with iolet links: find its entry and add what the later step left pending
-    int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
+    if constexpr (MODE != ADJ_OWN) {
+        // stream transpose: the link i of s pulled population i from j[i], so the
+        // population opp(i) of s went to j[i] (its link i pulled the other way), or
+        // was bounced back into the site's own direction i, or left through an iolet
+        g[0] = gin[tix<Q>(0, s)];
+        int32_t top = j[1];  // walls are negative, sites below n, ghost slots from n
 #pragma unroll
-    for (int i = 2; i < Q; ++i) top = max(top, j[i]);
-    int64_t kis = -1;
-    if (top >= n) {
-        int64_t l = -1;
+        for (int i = 1; i < Q; ++i) {
+            const int o = opp(i);
+            top = max(top, j[i]);
+            g[o] = j[i] >= n ? 0.f : gin[j[i] < 0 ? tix<Q>(i, s) : tix<Q>(o, j[i])];
+        }
+        if (top >= n) {
+            int64_t l = -1;
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if (l < 0 && j[i] >= n) l = ghost_link<Q>(G, n, j[i], i);
-        kis = I.link_is[l];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] += I.pend[kis * Q + i];
+            for (int i = 1; i < Q; ++i)
+                if (l < 0 && j[i] >= n) l = ghost_link<Q>(G, n, j[i], i);
+            iolet_terms<Q, ST, SC>(Ai, s, j, gin, G, I, I.link_is[l], n, g);
+        }
     }
-
-    float drho, mx, my, mz;
-    moments<Q>(d, drho, mx, my, mz);
-    const float rho = 1.0f + drho;
-    const float ir = 1.0f / rho;
-    const float ux = mx * ir, uy = my * ir, uz = mz * ir;
-    const float bx = keep * ux, by = keep * uy, bz = keep * uz;
-    const float ub2 = bx * bx + by * by + bz * bz;
-    const float ubu = bx * ux + by * uy + bz * uz;
-    // a = sum g_i dfeq_i/drho,  b = sum g_i dfeq_i/dm,  alpha term
-    float a = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, ga = 0.f;
+    if constexpr (MODE == ADJ_FINAL) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float cx = Lt::cx[i], cy = Lt::cy[i], cz = Lt::cz[i];
-        const float cub = cx * bx + cy * by + cz * bz;
-        const float cu = cx * ux + cy * uy + cz * uz;
-        const float wg = Lt::w[i] * g[i];
-        a += wg * (1.0f - 4.5f * cub * cub + 1.5f * ub2);
-        const float t = wg * (3.0f + 9.0f * cub);
-        b0 += t * cx - 3.0f * wg * bx;
-        b1 += t * cy - 3.0f * wg * by;
-        b2 += t * cz - 3.0f * wg * bz;
-        if constexpr (BRINK) ga += wg * (3.0f * cu + 9.0f * cub * cu - 3.0f * ubu);
-    }
-    b0 *= keep;
-    b1 *= keep;
-    b2 *= keep;
-    if constexpr (BRINK) alpha_hat[s] += (double)(-omega * rho * ga);
-
-    float fh[Q];
+        for (int i = 0; i < Q; ++i) gout[tix<Q>(i, s)] = g[i];
+        return;
+    } else {
+        float d[Q];
+        gather_pre<Q, ST, SC>(A, s, n, d, j);
+        float drho, mx, my, mz;
+        moments<Q>(d, drho, mx, my, mz);
+        const float rho = 1.0f + drho;
+        const float ir = 1.0f / rho;
+        const float ux = mx * ir, uy = my * ir, uz = mz * ir;
+        const float bx = keep * ux, by = keep * uy, bz = keep * uz;
+        const float ub2 = bx * bx + by * by + bz * bz;
+        const float ubu = bx * ux + by * uy + bz * uz;
+        // a = sum g_i dfeq_i/drho,  b = sum g_i dfeq_i/dm,  alpha term
+        float a = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, ga = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        fh[i] = (1.0f - omega) * g[i] +
-                omega * (a + (float)Lt::cx[i] * b0 + (float)Lt::cy[i] * b1 + (float)Lt::cz[i] * b2);
+        for (int i = 0; i < Q; ++i) {
+            const float cx = Lt::cx[i], cy = Lt::cy[i], cz = Lt::cz[i];
+            const float cub = cx * bx + cy * by + cz * bz;
+            const float cu = cx * ux + cy * uy + cz * uz;
+            const float wg = Lt::w[i] * g[i];
+            a += wg * (1.0f - 4.5f * cub * cub + 1.5f * ub2);
+            const float t = wg * (3.0f + 9.0f * cub);
+            b0 += t * cx - 3.0f * wg * bx;
+            b1 += t * cy - 3.0f * wg * by;
+            b2 += t * cz - 3.0f * wg * bz;
+            if constexpr (BRINK) ga += wg * (3.0f * cu + 9.0f * cub * cu - 3.0f * ubu);
+        }
+        b0 *= keep;
+        b1 *= keep;
+        b2 *= keep;
+        if constexpr (BRINK) alpha_hat[s] += (double)(-omega * rho * ga);
 
-    // wall-shear objective: dWSS/df_j = -(1 - omega/2) (t^.(c_j - u)) (n.(c_j - u))
-    if (wss_w) {
+        float fh[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            fh[i] = (1.0f - omega) * g[i] +
+                    omega * (a + (float)Lt::cx[i] * b0 + (float)Lt::cy[i] * b1 + (float)Lt::cz[i] * b2);
+
+        // wall-shear objective: dWSS/df_j = -(1 - omega/2) (t^.(c_j - u)) (n.(c_j - u))
         if (ws != 0.f) {
             const float nx = normal[s], ny = normal[n + s], nz = normal[2 * (int64_t)n + s];
             float tx, ty, tz;
@@ -337,65 +352,47 @@ __device__ inline void adj_scatter_group(
                 }
             }
         }
-    }
-
-    // push each adjoint to where the forward pulled the value from
-    gout[tix<Q>(0, s)] = fh[0];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        int dir;
-        int32_t site;
-        link_src(i, j[i], s, dir, site);
-        gout[tix<Q>(dir, site)] = fh[i];
-        // an iolet link: the population opp(i) of this site leaves the domain
-        if (j[i] >= n) gout[tix<Q>(opp(i), s)] = 0.0f;
+        for (int i = 0; i < Q; ++i) gout[tix<Q>(i, s)] = fh[i];
     }
-    if (kis >= 0) iolet_adjoint<Q, ST, SC>(A, s, j, fh, G, I, kis, n);
 }
 
-template <int Q, int ST, bool SC, bool BRINK>
-__global__ __launch_bounds__(kBlock) void k_adj_scatter(
-    const typename Store<ST>::T* __restrict__ A, const float* __restrict__ gin,
-    float* __restrict__ gout, Table tb, int32_t n, float omega,
-    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
-    const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
+template <int Q, int ST, bool SC, bool BRINK, int MODE>
+__global__ __launch_bounds__(kBlock) void k_adj_step(
+    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ Ai,
+    const float* __restrict__ gin, float* __restrict__ gout, Table tb, int32_t n,
+    int32_t xcd_group, float omega, const float* __restrict__ alpha,
+    double* __restrict__ alpha_hat, const float* __restrict__ wss_w,
+    const float* __restrict__ normal, Ghosts G, IoletAdj I) {
     __shared__ StageLds lds;
-    adj_scatter_group<Q, ST, SC, BRINK>(A, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w, normal,
-                                        G, I, (int32_t)blockIdx.x, lds);
+    adj_group<Q, ST, SC, BRINK, MODE>(A, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
+                                      normal, G, I, xcd_block((int32_t)blockIdx.x, xcd_group),
+                                      lds);
 }
 
-// A reverse step of one segment (blocks below nb) and a recompute step of the
-// next earlier segment (the other blocks) in one launch: the two touch disjoint
-// buffers, and for a lattice too small to fill the GPU each half runs beside the
-// other instead of after it.  The longer reverse half is dispatched first, so the
-// recompute workgroups fill the compute units as they drain.
-template <int Q, int ST, bool SC, bool BRINK>
+// A reverse step of one segment (blocks below nb, a multiple of 8 xcd_group) and a
+// recompute step of the next earlier segment (the other blocks) in one launch: the
+// two touch disjoint buffers, and for a lattice too small to fill the GPU each half
+// runs beside the other instead of after it.  The longer reverse half is
+// dispatched first, so the recompute workgroups fill the compute units as they
+// drain.
+template <int Q, int ST, bool SC, bool BRINK, int MODE>
 __global__ __launch_bounds__(kBlock) void k_adj_dual(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Ghosts Gf, int64_t t_next, int32_t nb, const typename Store<ST>::T* __restrict__ A,
-    const float* __restrict__ gin, float* __restrict__ gout, Table tb, int32_t n, float omega,
+    const typename Store<ST>::T* __restrict__ Ai, const float* __restrict__ gin,
+    float* __restrict__ gout, Table tb, int32_t n, int32_t xcd_group, float omega,
     const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
     __shared__ StageLds lds;
-    if ((int32_t)blockIdx.x < nb)
-        adj_scatter_group<Q, ST, SC, BRINK>(A, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
-                                            normal, G, I, (int32_t)blockIdx.x, lds);
+    const int32_t b = (int32_t)blockIdx.x;
+    if (b < nb)
+        adj_group<Q, ST, SC, BRINK, MODE>(A, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
+                                          normal, G, I, xcd_block(b, xcd_group), lds);
     else
-        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, (int32_t)blockIdx.x - nb,
-                                                      omega, alpha, Gf, t_next, lds);
-}
-
-// adds what the last reverse step left pending to the sites' own populations
-template <int Q>
-__global__ __launch_bounds__(kBlock) void k_adj_flush(float* __restrict__ gout, IoletAdj I) {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= I.S.count) return;
-    const int32_t s = I.S.site[k];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        gout[tix<Q>(i, s)] += I.pend[k * Q + i];
-        I.pend[k * Q + i] = 0.f;
-    }
+        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n,
+                                                      xcd_block(b - nb, xcd_group), omega, alpha,
+                                                      Gf, t_next, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,57 +421,110 @@ hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, con
     return hipGetLastError();
 }
 
-hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, const void* A,
-                           const float* gin, float* gout, float omega, const float* alpha,
-                           double* alpha_hat, const float* wss_w, const float* normal,
+// grid of four-tile workgroups, padded to whole XCD windows
+static int64_t adj_grid(int64_t n, int xcd_group) {
+    const int64_t nb = (int64_t)blocks(n);
+    return xcd_group > 0 ? ((nb + 8 * xcd_group - 1) / (8 * xcd_group)) * (8 * xcd_group) : nb;
+}
+
+// the kernel for one (mode, Brinkman) choice, as a function of the dispatch tag
+template <int MODE, bool BRINK, typename Tg>
+static hipError_t adj_step_mode(const Layout& L, const Ghosts& G, const IoletAdj& I,
+                                const void* A, const void* Ai, const float* gin, float* gout,
+                                float omega, const float* alpha, double* alpha_hat,
+                                const float* wss_w, const float* normal, int xcd_group,
+                                hipStream_t s) {
+    using T = typename Store<Tg::ST>::T;
+    k_adj_step<Tg::Q, Tg::ST, Tg::SC, BRINK, MODE>
+        <<<(unsigned)adj_grid(L.n, xcd_group), kBlock, 0, s>>>(
+            static_cast<const T*>(A), static_cast<const T*>(Ai), gin, gout, L.tb, (int32_t)L.n,
+            xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
+    return hipGetLastError();
+}
+
+template <int MODE, typename Tg>
+static hipError_t adj_step_brink(const Layout& L, const Ghosts& G, const IoletAdj& I,
+                                 const void* A, const void* Ai, const float* gin, float* gout,
+                                 float omega, const float* alpha, double* alpha_hat,
+                                 const float* wss_w, const float* normal, int xcd_group,
+                                 hipStream_t s) {
+    if (alpha && MODE != ADJ_FINAL)
+        return adj_step_mode<MODE, true, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha, alpha_hat,
+                                             wss_w, normal, xcd_group, s);
+    return adj_step_mode<MODE, false, Tg>(L, G, I, A, Ai, gin, gout, omega, nullptr, alpha_hat,
+                                          wss_w, normal, xcd_group, s);
+}
+
+hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, int mode,
+                           const void* A, const void* Ai, const float* gin, float* gout,
+                           float omega, const float* alpha, double* alpha_hat,
+                           const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s) {
     if (L.n == 0) return hipSuccess;
     return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
-        using T = typename Store<Tg::ST>::T;
-        if (alpha)
-            k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, true><<<blocks(L.n), kBlock, 0, s>>>(
-                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, alpha, alpha_hat,
-                wss_w, normal, G, I);
-        else
-            k_adj_scatter<Tg::Q, Tg::ST, Tg::SC, false><<<blocks(L.n), kBlock, 0, s>>>(
-                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
-                alpha_hat, wss_w, normal, G, I);
-        return hipGetLastError();
+        switch (mode) {
+            case ADJ_OWN:
+                return adj_step_brink<ADJ_OWN, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha,
+                                                   alpha_hat, wss_w, normal, xcd_group, s);
+            case ADJ_PULL:
+                return adj_step_brink<ADJ_PULL, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha,
+                                                    alpha_hat, wss_w, normal, xcd_group, s);
+            case ADJ_FINAL:
+                return adj_step_brink<ADJ_FINAL, Tg>(L, G, I, A, Ai, gin, gout, omega, nullptr,
+                                                     nullptr, nullptr, normal, xcd_group, s);
+        }
+        return hipErrorInvalidValue;
     });
+}
+
+template <int MODE, bool BRINK, typename Tg>
+static hipError_t adj_dual_mode(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
+                                int64_t t_next, const Ghosts& G, const IoletAdj& I,
+                                const void* A, const void* Ai, const float* gin, float* gout,
+                                float omega, const float* alpha, double* alpha_hat,
+                                const float* wss_w, const float* normal, int xcd_group,
+                                hipStream_t s) {
+    using T = typename Store<Tg::ST>::T;
+    const int64_t nb = adj_grid(L.n, xcd_group);
+    k_adj_dual<Tg::Q, Tg::ST, Tg::SC, BRINK, MODE><<<(unsigned)(2 * nb), kBlock, 0, s>>>(
+        static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, (int32_t)nb,
+        static_cast<const T*>(A), static_cast<const T*>(Ai), gin, gout, L.tb, (int32_t)L.n,
+        xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
+    return hipGetLastError();
+}
+
+template <int MODE, typename Tg>
+static hipError_t adj_dual_brink(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
+                                 int64_t t_next, const Ghosts& G, const IoletAdj& I,
+                                 const void* A, const void* Ai, const float* gin, float* gout,
+                                 float omega, const float* alpha, double* alpha_hat,
+                                 const float* wss_w, const float* normal, int xcd_group,
+                                 hipStream_t s) {
+    if (alpha)
+        return adj_dual_mode<MODE, true, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout, omega,
+                                             alpha, alpha_hat, wss_w, normal, xcd_group, s);
+    return adj_dual_mode<MODE, false, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout, omega,
+                                          nullptr, alpha_hat, wss_w, normal, xcd_group, s);
 }
 
 hipError_t launch_adj_dual(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
-                           int64_t t_next, const Ghosts& G, const IoletAdj& I, const void* A,
-                           const float* gin, float* gout, float omega, const float* alpha,
-                           double* alpha_hat, const float* wss_w, const float* normal,
+                           int64_t t_next, const Ghosts& G, const IoletAdj& I, int mode,
+                           const void* A, const void* Ai, const float* gin, float* gout,
+                           float omega, const float* alpha, double* alpha_hat,
+                           const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s) {
     if (L.n == 0) return hipSuccess;
-    const int32_t nb = (int32_t)blocks(L.n);
+    if (mode != ADJ_OWN && mode != ADJ_PULL) return hipErrorInvalidValue;
     return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
-        using T = typename Store<Tg::ST>::T;
-        if (alpha)
-            k_adj_dual<Tg::Q, Tg::ST, Tg::SC, true><<<2u * nb, kBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, nb,
-                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, alpha, alpha_hat,
-                wss_w, normal, G, I);
-        else
-            k_adj_dual<Tg::Q, Tg::ST, Tg::SC, false><<<2u * nb, kBlock, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, nb,
-                static_cast<const T*>(A), gin, gout, L.tb, (int32_t)L.n, omega, nullptr,
-                alpha_hat, wss_w, normal, G, I);
-        return hipGetLastError();
+        return mode == ADJ_OWN
+                   ? adj_dual_brink<ADJ_OWN, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout,
+                                                 omega, alpha, alpha_hat, wss_w, normal, xcd_group, s)
+                   : adj_dual_brink<ADJ_PULL, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout,
+                                                  omega, alpha, alpha_hat, wss_w, normal, xcd_group,
+                                                  s);
     });
-}
-
-hipError_t launch_adj_flush(int q, float* gout, const IoletAdj& I, hipStream_t s) {
-    if (I.S.count == 0) return hipSuccess;
-    if (q == 15)
-        k_adj_flush<15><<<blocks(I.S.count), kBlock, 0, s>>>(gout, I);
-    else
-        k_adj_flush<19><<<blocks(I.S.count), kBlock, 0, s>>>(gout, I);
-    return hipGetLastError();
 }
 
 }  // namespace hlb

@@ -32,11 +32,11 @@ hipError_t launch_objective(const Layout& L, const Ghosts& G, const void* A, con
                             const float* normal, float omega, double* part, double* q_out,
                             double* w_out, hipStream_t s);
 
-// The iolet part of one reverse step t.
+// The iolet terms of the stream transpose at step t (the step whose ghost values
+// are differentiated).
 struct IoletAdj {
     IoletSites S;           // sites with iolet links, sorted by site
     const int32_t* link_is; // entry in S of the site of each iolet link
-    float* pend;            // [S.count][q]: adjoint pending for the sites' own populations
     double t;               // boundary time of the step
     int32_t outlet;         // iolet of the flux objective
     const double* q_tape;   // Q(t) of the window steps
@@ -46,23 +46,38 @@ struct IoletAdj {
     int32_t nbasis;
 };
 
-// One reverse step t: gin = dJ/dA_{t+1} -> gout = dJ/dA_t (FP32, tiled), accumulating
-// dJ/dalpha (FP64 per site) and the inlet-coefficient adjoints (FP64 per link);
-// wss_w: per-site weight of the wall-shear term, or null outside the window.  What
-// the iolet sites send to their own populations stays in I.pend until the next
-// reverse step reads it, or launch_adj_flush adds it to gout.
-hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, const void* A,
-                           const float* gin, float* gout, float omega, const float* alpha,
-                           double* alpha_hat, const float* wss_w, const float* normal,
+// The reverse sweep in pull form.  Between kernels of one segment the sweep holds
+// fhat_t = dJ/df_t, the adjoint of the pre-collision populations; at segment ends
+// it holds ghat_t = dJ/dA_t.  Every kernel writes only its own sites' rows
+// (coalesced), so nothing is scattered and nothing waits for another thread.
+//   ADJ_OWN   ghat_{t+1} (gin, own rows) -> fhat_t: the transposed collision of step
+//             t at the taped state A (= A_t), the wall-shear term, dJ/dalpha.
+//   ADJ_PULL  fhat_{t+1} (gin) -> fhat_t: first ghat_{t+1} by the stream transpose
+//             of step t + 1 (population k of site s was read by the link of the
+//             site s + c_k, i.e. by the link opp(k) of s pulling the other way, by
+//             s itself across a wall, or by nobody across an iolet) plus the iolet
+//             terms of step t + 1 at the taped state Ai (= A_{t+1}, ghosts and
+//             I for time t + 1), then as ADJ_OWN.
+//   ADJ_FINAL fhat_t (gin) -> ghat_t (gout): the stream transpose of step t alone,
+//             iolet terms at Ai (= A_t).
+enum AdjMode { ADJ_OWN = 0, ADJ_PULL = 1, ADJ_FINAL = 2 };
+
+// wss_w: per-site weight of the wall-shear term of step t, or null outside the
+// window; xcd_group: the workgroup-to-XCD grouping of the forward step.
+hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, int mode,
+                           const void* A, const void* Ai, const float* gin, float* gout,
+                           float omega, const float* alpha, double* alpha_hat,
+                           const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s);
-hipError_t launch_adj_flush(int q, float* gout, const IoletAdj& I, hipStream_t s);
 
 // One launch of two independent steps: the recompute step src -> dst at t_next
-// (ghosts Gf) and the reverse step of launch_adj_step (no interpolated walls).
+// (ghosts Gf) and a reverse step of launch_adj_step in mode ADJ_OWN or ADJ_PULL (no
+// interpolated walls).
 hipError_t launch_adj_dual(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
-                           int64_t t_next, const Ghosts& G, const IoletAdj& I, const void* A,
-                           const float* gin, float* gout, float omega, const float* alpha,
-                           double* alpha_hat, const float* wss_w, const float* normal,
+                           int64_t t_next, const Ghosts& G, const IoletAdj& I, int mode,
+                           const void* A, const void* Ai, const float* gin, float* gout,
+                           float omega, const float* alpha, double* alpha_hat,
+                           const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s);
 
 }  // namespace hlb

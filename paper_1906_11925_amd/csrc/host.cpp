@@ -321,7 +321,6 @@ struct hemelb_lb {
     double* alpha_hat = nullptr;
     double* theta_acc = nullptr;
     int32_t nbasis = 1;
-    float* is_pend = nullptr;  // adjoint pending for iolet sites' own populations [n_is][q]
     int32_t* is_link = nullptr;  // entry of each iolet link's site among the iolet sites
     int32_t* is_site = nullptr;
     int32_t* is_lo = nullptr;
@@ -392,7 +391,7 @@ void release(hemelb_lb* h) {
                     h->d_out_links, h->d_dome,  h->d_wss_w,    h->d_qtape,   h->d_wtape,
                     h->d_opart,
                     h->ghat[0],   h->ghat[1],   h->alpha_hat,  h->theta_acc, h->is_site,
-                    h->is_pend,   h->r_grid,    h->r_near,     h->r_rec,     h->r_vals,    h->r_lut,
+                    h->r_grid,    h->r_near,     h->r_rec,     h->r_vals,    h->r_lut,
                     h->is_lo,     h->is_hi,     h->d_vals};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -1266,7 +1265,7 @@ int recompute_step(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Seri
 hlb::IoletAdj iolet_adj(const hemelb_lb* h, int64_t t) {
     const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
     const bool inw = t >= h->w0 && t < h->w1;
-    return hlb::IoletAdj{S,          h->is_link,        h->is_pend,  (double)t,     h->obj_outlet,
+    return hlb::IoletAdj{S,          h->is_link,        (double)t,     h->obj_outlet,
                          h->d_qtape, inw ? t - h->w0 : -1, h->q_target, h->theta_acc, h->nbasis};
 }
 
@@ -1275,42 +1274,54 @@ const float* wss_weights(const hemelb_lb* h, int64_t t) {
     return t >= h->w0 && t < h->w1 ? h->d_wss_w : nullptr;
 }
 
-// reverse step t0 + m from the recomputed tape
+// Reverse kernel of step t0 + m of a segment of `steps` steps (tape[m] = A_{t0+m}):
+// the segment's last step starts from dJ/dA_{t0+steps}, the others from the fhat
+// of the step after.
+int reverse_mode(int64_t m, int64_t steps) { return m == steps - 1 ? hlb::ADJ_OWN : hlb::ADJ_PULL; }
+
 int reverse_step(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
-                 int64_t m, hipStream_t stream) {
+                 int64_t m, int64_t steps, hipStream_t stream) {
     const int64_t t = t0 + m;
-    HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t), tape[m],
-                                 h->ghat[h->gcur], h->ghat[h->gcur ^ 1], h->omega, h->alpha,
-                                 h->alpha_hat, wss_weights(h, t), h->normal, stream),
+    const int mode = reverse_mode(m, steps);
+    HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t + 1), mode,
+                                 tape[m], tape[m + 1], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
+                                 h->omega, h->alpha, h->alpha_hat, wss_weights(h, t), h->normal,
+                                 h->xcd_group, stream),
             "adjoint step");
     h->gcur ^= 1;
     return HEMELB_OK;
 }
 
 // recompute step mf of the segment at tf0 (tape tf, series sf) and reverse step
-// mr of the segment at tr0 (tape tr, series sr) in one launch
+// mr of the segment at tr0 of nr_steps steps (tape tr, series sr) in one launch
 int dual_step(hemelb_lb* h, std::vector<void*>& tf, const hemelb_lb::Series& sf, int64_t tf0,
               int64_t mf, std::vector<void*>& tr, const hemelb_lb::Series& sr, int64_t tr0,
-              int64_t mr, hipStream_t stream) {
+              int64_t mr, int64_t nr_steps, hipStream_t stream) {
     const hlb::Layout L = h->layout();
     const hlb::Ghosts Gf = segment_ghosts(h, sf);
     if (mf == 0 || !hlb::ghosts_fused())
         HIP_TRY(hlb::launch_ghost_fill(L, Gf, tf[mf], tf0 + mf, stream), "recompute ghosts");
     const int64_t t = tr0 + mr;
     HIP_TRY(hlb::launch_adj_dual(L, Gf, tf[mf], tf[mf + 1], tf0 + mf + 1, segment_ghosts(h, sr),
-                                 iolet_adj(h, t), tr[mr], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
-                                 h->omega, h->alpha, h->alpha_hat, wss_weights(h, t), h->normal,
-                                 stream),
+                                 iolet_adj(h, t + 1), reverse_mode(mr, nr_steps), tr[mr],
+                                 tr[mr + 1], h->ghat[h->gcur], h->ghat[h->gcur ^ 1], h->omega,
+                                 h->alpha, h->alpha_hat, wss_weights(h, t), h->normal,
+                                 h->xcd_group, stream),
             "adjoint dual step");
     h->gcur ^= 1;
     return HEMELB_OK;
 }
 
-// the iolet terms still pending after the last reverse step of a segment
-int end_reverse(hemelb_lb* h, hipStream_t stream) {
-    const hlb::IoletSites S{h->n_is, h->is_site, h->is_lo, h->is_hi};
-    const hlb::IoletAdj I{S, h->is_link, h->is_pend, 0.0, -1, nullptr, -1, 0.0, nullptr, 0};
-    HIP_TRY(hlb::launch_adj_flush(h->q, h->ghat[h->gcur], I, stream), "adjoint flush");
+// end of a segment at t0 (tape[0] = A_t0): the stream transpose of step t0 alone,
+// fhat_t0 -> dJ/dA_t0
+int end_reverse(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
+                hipStream_t stream) {
+    HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t0),
+                                 hlb::ADJ_FINAL, nullptr, tape[0], h->ghat[h->gcur],
+                                 h->ghat[h->gcur ^ 1], h->omega, nullptr, nullptr, nullptr,
+                                 h->normal, h->xcd_group, stream),
+            "adjoint segment end");
+    h->gcur ^= 1;
     return HEMELB_OK;
 }
 
@@ -2040,9 +2051,7 @@ static int adjoint_begin_impl(hemelb_lb_t h, int64_t max_segment) {
         if ((rc = dev_upload(h, &h->is_lo, lo, "iolet sites"))) return rc;
         if ((rc = dev_upload(h, &h->is_hi, hi, "iolet sites"))) return rc;
         h->n_is = (int64_t)st.size();
-        if ((rc = dev_alloc(h, &h->is_pend, (size_t)h->n_is * h->q, "iolet pending"))) return rc;
     }
-    if (h->is_pend) HIP_TRY(hlb::launch_zero_words(h->is_pend, h->n_is * h->q, h->stream), "zero");
     h->gcur = 0;
     hlb::Layout Lg = h->layout();
     Lg.storage = HEMELB_STORE_F32;
@@ -2073,8 +2082,8 @@ static int adjoint_segment_impl(hemelb_lb_t h, const void* checkpoint, int64_t t
     int rc = begin_recompute(h, h->tape, h->series[0], checkpoint, t0, steps, h->stream);
     for (int64_t m = 0; m < steps && !rc; ++m) rc = recompute_step(h, h->tape, h->series[0], t0, m, h->stream);
     for (int64_t m = steps - 1; m >= 0 && !rc; --m)
-        rc = reverse_step(h, h->tape, h->series[0], t0, m, h->stream);
-    if (!rc) rc = end_reverse(h, h->stream);
+        rc = reverse_step(h, h->tape, h->series[0], t0, m, steps, h->stream);
+    if (!rc) rc = end_reverse(h, h->tape, h->series[0], t0, h->stream);
     if (rc) return rc;
     h->adj_t = t0;
     return HEMELB_OK;
@@ -2134,14 +2143,14 @@ static int adjoint_run_impl(hemelb_lb_t h, const void* const* checkpoints, const
             const int64_t mr = steps[k] - 1 - m;
             if (m < steps[k] && m < nr)
                 rc = dual_step(h, tf, h->series[nb], t0[k - 1], m, tr, h->series[b], t0[k], mr,
-                               h->stream);
+                               steps[k], h->stream);
             else if (m < steps[k])
-                rc = reverse_step(h, tr, h->series[b], t0[k], mr, h->stream);
+                rc = reverse_step(h, tr, h->series[b], t0[k], mr, steps[k], h->stream);
             else
                 rc = recompute_step(h, tf, h->series[nb], t0[k - 1], m, h->stream);
             if (rc) return rc;
         }
-        if ((rc = end_reverse(h, h->stream))) return rc;
+        if ((rc = end_reverse(h, tr, h->series[b], t0[k], h->stream))) return rc;
     }
     h->adj_t = t0[0];
     return HEMELB_OK;
@@ -2218,8 +2227,8 @@ static int adjoint_recorded_impl(hemelb_lb_t h) {
     h->ghosts_ready = false;
     int rc = fill_segment_series(h, h->series[0], h->rec_t0, steps + 1, h->stream);
     for (int64_t m = steps - 1; m >= 0 && !rc; --m)
-        rc = reverse_step(h, h->rec, h->series[0], h->rec_t0, m, h->stream);
-    if (!rc) rc = end_reverse(h, h->stream);
+        rc = reverse_step(h, h->rec, h->series[0], h->rec_t0, m, steps, h->stream);
+    if (!rc) rc = end_reverse(h, h->rec, h->series[0], h->rec_t0, h->stream);
     if (rc) return rc;
     h->adj_t = h->rec_t0;
     return HEMELB_OK;

@@ -47,16 +47,15 @@ hipError_t launch_objective(const Layout&, const Ghosts&, const void*, const Obj
                             const float*, float, double*, double*, double*, hipStream_t) {
     return hipErrorNoDevice;
 }
-hipError_t launch_adj_step(const Layout&, const Ghosts&, const IoletAdj&, const void*,
-                           const float*, float*, float, const float*, double*, const float*,
-                           const float*, hipStream_t) {
+hipError_t launch_adj_step(const Layout&, const Ghosts&, const IoletAdj&, int, const void*,
+                           const void*, const float*, float*, float, const float*, double*,
+                           const float*, const float*, int, hipStream_t) {
     return hipErrorNoDevice;
 }
-hipError_t launch_adj_flush(int, float*, const IoletAdj&, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_adj_dual(const Layout&, const Ghosts&, const void*, void*, int64_t,
-                           const Ghosts&, const IoletAdj&, const void*, const float*, float*,
-                           float, const float*, double*, const float*, const float*,
-                           hipStream_t) {
+                           const Ghosts&, const IoletAdj&, int, const void*, const void*,
+                           const float*, float*, float, const float*, double*, const float*,
+                           const float*, int, hipStream_t) {
     return hipErrorNoDevice;
 }
 hipError_t launch_render(const RenderVolume&, const RenderView&, const float*, float*,
