@@ -254,9 +254,11 @@ struct hemelb_lb {
     bool ghosts_ready = false;  // A[cur]'s ghost slots hold the incoming values for time t
     int xcd_group = 16;  // consecutive workgroups per XCD (measured best at 8-16)
     // stream-collide workgroups that copy their own tiles' populations into LDS
-    // (block addressing only): with FP32 storage 8 tiles for D3Q15 and 4 for D3Q19
-    // (fastest on the 53M-site tree; the copy keeps the in-group pulls off the L1,
-    // which then holds the other tiles' lines), none with 16-bit storage (slower)
+    // (block addressing only; the copy keeps the in-group pulls off the L1, which
+    // then holds the other tiles' lines).  FP32 storage: 8 tiles for D3Q15 lattices
+    // of 4M sites or more, else 4; none for lattices of fewer than 256 four-tile
+    // groups (too few workgroups to hide the copy) and none with 16-bit storage
+    // (slower)
     int stage_tiles = 0;
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
@@ -1483,7 +1485,9 @@ static int init_handle(hemelb_lb* h, hemelb_lb_t* out, const hemelb_lb_desc_t* d
     h->omega = std::isinf(d->tau) ? 0.0f : (float)(1.0 / d->tau);
     h->stream = static_cast<hipStream_t>(d->stream);
     if (const char* e = getenv("HEMELB_XCD_GROUP")) h->xcd_group = std::max(0, atoi(e));
-    h->stage_tiles = h->storage == HEMELB_STORE_F32 ? (h->q == 15 ? 8 : 4) : 0;
+    h->stage_tiles = 0;
+    if (h->storage == HEMELB_STORE_F32 && (d->n_sites + 255) / 256 >= 256)
+        h->stage_tiles = h->q == 15 && d->n_sites >= ((int64_t)1 << 22) ? 8 : 4;
     if (const char* e = getenv("HEMELB_STAGE_TILES")) {
         const int v = atoi(e);
         h->stage_tiles = (v == 4 || v == 8 || v == 16) ? v : 0;
