@@ -33,9 +33,13 @@ COMPILE_FLAGS = [
 ]
 
 
+# the profiler's marker library (named ranges around the entry points)
+LIBS = ["-lrocprofiler-sdk-roctx", "-lpthread"]
+
+
 def command(out=LIB):
     """One hipcc command that compiles and links every source."""
-    return [hipcc(), *COMPILE_FLAGS, "-shared", *SOURCES, "-lpthread", "-o", out]
+    return [hipcc(), *COMPILE_FLAGS, "-shared", *SOURCES, *LIBS, "-o", out]
 
 
 def compile_command(src, obj):
@@ -43,7 +47,7 @@ def compile_command(src, obj):
 
 
 def link_command(objs, out):
-    return [hipcc(), "--offload-arch=gfx950", "-shared", *objs, "-lpthread", "-o", out]
+    return [hipcc(), "--offload-arch=gfx950", "-shared", *objs, *LIBS, "-o", out]
 
 
 # Sanitizer builds of the host code (the planner and its thread pool) for the CPU.
@@ -75,7 +79,7 @@ def sanitized_command(kind, sources, out):
         "-I", os.path.join(ROOT, "include"),
         *sources,
         HOST_SOURCE,
-        "-lpthread",
+        *LIBS,
         "-o", out,
     ]
 

@@ -22,6 +22,7 @@
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "render.hpp"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 namespace {
 
@@ -1329,6 +1330,15 @@ int end_reverse(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series&
 
 }  // namespace
 
+// A named range on the profiler's timeline (rocprofv3 --marker-trace) around one
+// entry point, so a trace shows which call issued which kernels.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
 extern "C" {
 
 const char* hemelb_lb_last_error(void) { return g_err.c_str(); }
@@ -1444,6 +1454,7 @@ static int links_impl(const uint8_t* labels, const int32_t shape[3], const int32
 
 int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t periodic[3],
                     int32_t lattice, int64_t* n_sites, int32_t* coords, int32_t* nbr) {
+    const Range range("hemelb_lb_links");
     return no_throw([&] { return links_impl(labels, shape, periodic, lattice, n_sites, coords, nbr); });
 }
 
@@ -1468,6 +1479,7 @@ static int plan_impl(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
 }
 
 int hemelb_lb_plan(const hemelb_lb_desc_t* d, hemelb_lb_info_t* info) {
+    const Range range("hemelb_lb_plan");
     return no_throw([&] { return plan_impl(d, info); });
 }
 
@@ -1619,16 +1631,19 @@ static int create_impl(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
 }
 
 int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* d) {
+    const Range range("hemelb_lb_create");
     return no_throw([&] { return create_impl(out, d); });
 }
 
 int hemelb_lb_destroy(hemelb_lb_t h) {
+    const Range range("hemelb_lb_destroy");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     release(h);
     return HEMELB_OK;
 }
 
 int hemelb_lb_step(hemelb_lb_t h, int64_t n) {
+    const Range range("hemelb_lb_step");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (n < 0) return fail(HEMELB_EINVAL, "negative step count");
     if (h->rec_t0 >= 0 && h->t + n > h->rec_t0 + (int64_t)h->rec.size() - 1)
@@ -1650,6 +1665,7 @@ int hemelb_lb_step(hemelb_lb_t h, int64_t n) {
 }
 
 int hemelb_lb_sync(hemelb_lb_t h) {
+    const Range range("hemelb_lb_sync");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
     if (h->check_every > 0) return check_flag(h);
@@ -1676,6 +1692,7 @@ int hemelb_lb_set_stream(hemelb_lb_t h, void* stream) {
 }
 
 int hemelb_lb_observables(hemelb_lb_t h, float* p, float* u, float* wss) {
+    const Range range("hemelb_lb_observables");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     const void* A = h->streamed ? h->A[h->cur ^ 1] : h->A[h->cur];
     HIP_TRY(hlb::launch_observables(h->layout(), A, h->streamed ? 1 : 0, h->omega, h->perm,
@@ -1685,6 +1702,7 @@ int hemelb_lb_observables(hemelb_lb_t h, float* p, float* u, float* wss) {
 }
 
 int hemelb_lb_totals(hemelb_lb_t h, double out[4]) {
+    const Range range("hemelb_lb_totals");
     if (!h || !out) return fail(HEMELB_EINVAL, "NULL argument");
     HIP_TRY(hlb::launch_totals(h->layout(), h->A[h->cur], h->partial, h->nparts, h->tot, h->flag,
                                h->stream),
@@ -1696,6 +1714,7 @@ int hemelb_lb_totals(hemelb_lb_t h, double out[4]) {
 }
 
 int hemelb_lb_totals_noalloc(hemelb_lb_t h, double* out) {
+    const Range range("hemelb_lb_totals_noalloc");
     if (!h || !out) return fail(HEMELB_EINVAL, "NULL argument");
     if (hlb::totals_parts(h->n) > hlb::totals_scratch_parts())
         return fail(HEMELB_EINVAL, "%lld reduction blocks exceed the scratch of %lld",
@@ -1716,12 +1735,14 @@ static int state_io(hemelb_lb_t h, void* ext, int mode) {
 }
 
 int hemelb_lb_get_state(hemelb_lb_t h, void* dst, int64_t* t) {
+    const Range range("hemelb_lb_get_state");
     if (!h || (!dst && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (t) *t = h->t;
     return state_io(h, dst, 0);
 }
 
 int hemelb_lb_set_state(hemelb_lb_t h, const void* src, int64_t t) {
+    const Range range("hemelb_lb_set_state");
     if (!h || (!src && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
     if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is being recorded");
@@ -1732,11 +1753,13 @@ int hemelb_lb_set_state(hemelb_lb_t h, const void* src, int64_t t) {
 }
 
 int hemelb_lb_get_deviations(hemelb_lb_t h, float* dst) {
+    const Range range("hemelb_lb_get_deviations");
     if (!h || (!dst && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     return state_io(h, dst, 2);
 }
 
 int hemelb_lb_set_deviations(hemelb_lb_t h, const float* src, int64_t t) {
+    const Range range("hemelb_lb_set_deviations");
     if (!h || (!src && h->n > 0)) return fail(HEMELB_EINVAL, "NULL argument");
     if (t < 0) return fail(HEMELB_EINVAL, "negative time");
     if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is being recorded");
@@ -1840,6 +1863,7 @@ static int render_impl(hemelb_lb_t h, const float* values, const hemelb_view_t* 
 }
 
 int hemelb_lb_render(hemelb_lb_t h, const float* values, const hemelb_view_t* view, float* image) {
+    const Range range("hemelb_lb_render");
     return no_throw([&] { return render_impl(h, values, view, image); });
 }
 
@@ -1881,6 +1905,7 @@ static int set_iolet_impl(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
 }
 
 int hemelb_lb_set_iolet(hemelb_lb_t h, int32_t k, const hemelb_iolet_t* io) {
+    const Range range("hemelb_lb_set_iolet");
     return no_throw([&] { return set_iolet_impl(h, k, io); });
 }
 
@@ -1911,6 +1936,7 @@ static int set_alpha_impl(hemelb_lb_t h, const float* alpha) {
 }
 
 int hemelb_lb_set_alpha(hemelb_lb_t h, const float* alpha) {
+    const Range range("hemelb_lb_set_alpha");
     return no_throw([&] { return set_alpha_impl(h, alpha); });
 }
 
@@ -1972,10 +1998,12 @@ static int set_objective_impl(hemelb_lb_t h, const hemelb_objective_t* obj) {
 }
 
 int hemelb_lb_set_objective(hemelb_lb_t h, const hemelb_objective_t* obj) {
+    const Range range("hemelb_lb_set_objective");
     return no_throw([&] { return set_objective_impl(h, obj); });
 }
 
 int hemelb_lb_objective_value(hemelb_lb_t h, double* J, double* flux_term, double* wss_term) {
+    const Range range("hemelb_lb_objective_value");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (!h->obj_set) return fail(HEMELB_EORDER, "no objective set");
     if (h->t < h->w1)
@@ -2000,6 +2028,7 @@ int hemelb_lb_objective_value(hemelb_lb_t h, double* J, double* flux_term, doubl
 }
 
 int hemelb_lb_objective_flux(hemelb_lb_t h, double* q) {
+    const Range range("hemelb_lb_objective_flux");
     if (!h || !q) return fail(HEMELB_EINVAL, "NULL argument");
     if (!h->obj_set) return fail(HEMELB_EORDER, "no objective set");
     HIP_TRY(hipStreamSynchronize(h->stream), "sync");
@@ -2068,6 +2097,7 @@ static int adjoint_begin_impl(hemelb_lb_t h, int64_t max_segment) {
 }
 
 int hemelb_lb_adjoint_begin(hemelb_lb_t h, int64_t max_segment) {
+    const Range range("hemelb_lb_adjoint_begin");
     return no_throw([&] { return adjoint_begin_impl(h, max_segment); });
 }
 
@@ -2094,6 +2124,7 @@ static int adjoint_segment_impl(hemelb_lb_t h, const void* checkpoint, int64_t t
 }
 
 int hemelb_lb_adjoint_segment(hemelb_lb_t h, const void* checkpoint, int64_t t0, int64_t steps) {
+    const Range range("hemelb_lb_adjoint_segment");
     return no_throw([&] { return adjoint_segment_impl(h, checkpoint, t0, steps); });
 }
 
@@ -2162,6 +2193,7 @@ static int adjoint_run_impl(hemelb_lb_t h, const void* const* checkpoints, const
 
 int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const int64_t* t0,
                           const int64_t* steps, int64_t nseg) {
+    const Range range("hemelb_lb_adjoint_run");
     return no_throw([&] { return adjoint_run_impl(h, checkpoints, t0, steps, nseg); });
 }
 
@@ -2194,10 +2226,12 @@ static int record_impl(hemelb_lb_t h, int64_t max_steps) {
 }
 
 int hemelb_lb_record(hemelb_lb_t h, int64_t max_steps) {
+    const Range range("hemelb_lb_record");
     return no_throw([&] { return record_impl(h, max_steps); });
 }
 
 int hemelb_lb_record_end(hemelb_lb_t h) {
+    const Range range("hemelb_lb_record_end");
     if (!h) return fail(HEMELB_EINVAL, "NULL handle");
     if (h->rec_t0 < 0) return HEMELB_OK;
     HIP_TRY(hipSetDevice(h->device), "set device");
@@ -2239,6 +2273,7 @@ static int adjoint_recorded_impl(hemelb_lb_t h) {
 }
 
 int hemelb_lb_adjoint_recorded(hemelb_lb_t h) {
+    const Range range("hemelb_lb_adjoint_recorded");
     return no_throw([&] { return adjoint_recorded_impl(h); });
 }
 
@@ -2275,6 +2310,7 @@ static int adjoint_grads_impl(hemelb_lb_t h, double* dtheta, double* dalpha) {
 }
 
 int hemelb_lb_adjoint_grads(hemelb_lb_t h, double* dtheta, double* dalpha) {
+    const Range range("hemelb_lb_adjoint_grads");
     return no_throw([&] { return adjoint_grads_impl(h, dtheta, dalpha); });
 }
 
@@ -2289,6 +2325,7 @@ static int get_adjoint_impl(hemelb_lb_t h, float* dst) {
 }
 
 int hemelb_lb_get_adjoint(hemelb_lb_t h, float* dst) {
+    const Range range("hemelb_lb_get_adjoint");
     return no_throw([&] { return get_adjoint_impl(h, dst); });
 }
 
