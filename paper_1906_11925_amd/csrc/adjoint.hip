@@ -375,24 +375,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(
 // two touch disjoint buffers, and for a lattice too small to fill the GPU each half
 // runs beside the other instead of after it.  The longer reverse half is
 // dispatched first, so the recompute workgroups fill the compute units as they
-// drain.
-template <int Q, int ST, bool SC, bool BRINK, int MODE>
+// drain.  With SREC (FP32 storage, block addressing, halfway walls) the recompute
+// half is the forward step that first copies its four tiles' populations into LDS.
+template <int Q, int ST, bool SC, bool BRINK, int MODE, bool SREC>
 __global__ __launch_bounds__(kBlock) void k_adj_dual(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Ghosts Gf, int64_t t_next, int32_t nb, const typename Store<ST>::T* __restrict__ A,
     const typename Store<ST>::T* __restrict__ Ai, const float* __restrict__ gin,
-    float* __restrict__ gout, Table tb, int32_t n, int32_t xcd_group, float omega,
-    const float* __restrict__ alpha, double* __restrict__ alpha_hat,
+    float* __restrict__ gout, Table tb, int32_t n, int32_t tiles_alloc, int32_t xcd_group,
+    float omega, const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal, Ghosts G, IoletAdj I) {
-    __shared__ StageLds lds;
+    __shared__ StageLds lds[1];
     const int32_t b = (int32_t)blockIdx.x;
-    if (b < nb)
+    if (b < nb) {
         adj_group<Q, ST, SC, BRINK, MODE>(A, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
-                                          normal, G, I, xcd_block(b, xcd_group), lds);
-    else
-        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n,
-                                                      xcd_block(b - nb, xcd_group), omega, alpha,
-                                                      Gf, t_next, lds);
+                                          normal, G, I, xcd_block(b, xcd_group), lds[0]);
+        return;
+    }
+    const int32_t g = xcd_block(b - nb, xcd_group);
+    if constexpr (SREC) {
+        __shared__ typename Store<ST>::T pops[4][Q][kTile];
+        stream_collide_staged<Q, ST, SC, BRINK, 4>(src, dst, tb, n, tiles_alloc, 4 * g, omega, alpha,
+                                                   Gf, t_next, pops, lds);
+    } else {
+        stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, g, omega, alpha, Gf, t_next,
+                                                      lds[0]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -478,7 +486,7 @@ hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, 
     });
 }
 
-template <int MODE, bool BRINK, typename Tg>
+template <int MODE, bool BRINK, bool SREC, typename Tg>
 static hipError_t adj_dual_mode(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
                                 int64_t t_next, const Ghosts& G, const IoletAdj& I,
                                 const void* A, const void* Ai, const float* gin, float* gout,
@@ -487,10 +495,10 @@ static hipError_t adj_dual_mode(const Layout& L, const Ghosts& Gf, const void* s
                                 hipStream_t s) {
     using T = typename Store<Tg::ST>::T;
     const int64_t nb = adj_grid(L.n, xcd_group);
-    k_adj_dual<Tg::Q, Tg::ST, Tg::SC, BRINK, MODE><<<(unsigned)(2 * nb), kBlock, 0, s>>>(
+    k_adj_dual<Tg::Q, Tg::ST, Tg::SC, BRINK, MODE, SREC><<<(unsigned)(2 * nb), kBlock, 0, s>>>(
         static_cast<const T*>(src), static_cast<T*>(dst), Gf, t_next, (int32_t)nb,
         static_cast<const T*>(A), static_cast<const T*>(Ai), gin, gout, L.tb, (int32_t)L.n,
-        xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
+        (int32_t)(L.slots / kTile), xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
     return hipGetLastError();
 }
 
@@ -501,11 +509,21 @@ static hipError_t adj_dual_brink(const Layout& L, const Ghosts& Gf, const void* 
                                  float omega, const float* alpha, double* alpha_hat,
                                  const float* wss_w, const float* normal, int xcd_group,
                                  hipStream_t s) {
+    // the recompute half stages its populations where the forward step would
+    const bool srec = Tg::ST == ST_F32 && L.stage_tiles > 0 && L.tb.grp && !L.bfl;
     if (alpha)
-        return adj_dual_mode<MODE, true, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout, omega,
-                                             alpha, alpha_hat, wss_w, normal, xcd_group, s);
-    return adj_dual_mode<MODE, false, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin, gout, omega,
-                                          nullptr, alpha_hat, wss_w, normal, xcd_group, s);
+        return srec ? adj_dual_mode<MODE, true, true, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai,
+                                                          gin, gout, omega, alpha, alpha_hat,
+                                                          wss_w, normal, xcd_group, s)
+                    : adj_dual_mode<MODE, true, false, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai,
+                                                           gin, gout, omega, alpha, alpha_hat,
+                                                           wss_w, normal, xcd_group, s);
+    return srec ? adj_dual_mode<MODE, false, true, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin,
+                                                       gout, omega, nullptr, alpha_hat, wss_w,
+                                                       normal, xcd_group, s)
+                : adj_dual_mode<MODE, false, false, Tg>(L, Gf, src, dst, t_next, G, I, A, Ai, gin,
+                                                        gout, omega, nullptr, alpha_hat, wss_w,
+                                                        normal, xcd_group, s);
 }
 
 hipError_t launch_adj_dual(const Layout& L, const Ghosts& Gf, const void* src, void* dst,
