@@ -394,9 +394,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_dual(
     }
     const int32_t g = xcd_block(b - nb, xcd_group);
     if constexpr (SREC) {
-        __shared__ typename Store<ST>::T pops[4][Q][kTile];
-        stream_collide_staged<Q, ST, SC, BRINK, 4>(src, dst, tb, n, tiles_alloc, 4 * g, omega, alpha,
-                                                   Gf, t_next, pops, lds);
+        __shared__ __attribute__((aligned(16))) typename Store<ST>::T pops[4][Q][kTile];
+        stream_collide_staged<Q, ST, SC, BRINK, 4, true>(src, dst, tb, n, tiles_alloc, 4 * g,
+                                                         omega, alpha, Gf, t_next, pops, lds);
     } else {
         stream_collide_group<Q, ST, SC, BRINK, false>(src, dst, tb, n, g, omega, alpha, Gf, t_next,
                                                       lds[0]);

@@ -261,6 +261,8 @@ struct hemelb_lb {
     // groups (too few workgroups to hide the copy) and none with 16-bit storage
     // (slower)
     int stage_tiles = 0;
+    // the FP32 staging copy uses loads that write LDS directly
+    bool lds_dma = true;
     int64_t check_every = 0;
     std::atomic<bool> cancel{false};
 
@@ -336,7 +338,7 @@ struct hemelb_lb {
                            hlb::Table{tbl, t16, toff, tlist, brec, gmask, bnbr, tblock,
                                       reinterpret_cast<const uint4*>(gblob), grp, nfluid, nblocks,
                                       (int32_t)n},
-                           bfl, stage_tiles};
+                           bfl, stage_tiles, lds_dma};
     }
     hlb::Ghosts ghosts() const {
         return hlb::Ghosts{nghost,  g_slot,   g_cell_link, g_site,  g_dir,   g_iolet,
@@ -1504,6 +1506,7 @@ static int init_handle(hemelb_lb* h, hemelb_lb_t* out, const hemelb_lb_desc_t* d
         const int v = atoi(e);
         h->stage_tiles = (v == 4 || v == 8 || v == 16) ? v : 0;
     }
+    if (const char* e = getenv("HEMELB_LDS_DMA")) h->lds_dma = atoi(e) != 0;
     (void)hipGetDevice(&h->device);
     const int q = h->q;
     const int64_t n = h->n;

@@ -50,17 +50,18 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide(
                                                 alpha, G, t_next, lds);
 }
 
-// workgroups of W tiles with their own populations staged in LDS (block addressing)
-template <int Q, int ST, bool SC, bool BRINK, int W>
+// workgroups of W tiles with their own populations staged in LDS (block addressing);
+// DMA: the copy writes LDS directly (FP32)
+template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA>
 __global__ __launch_bounds__(W * kTile) void k_stream_collide_staged(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t tiles_alloc, int32_t xcd_group, float omega,
     const float* __restrict__ alpha, Ghosts G, int64_t t_next) {
-    __shared__ typename Store<ST>::T pops[W][Q][kTile];
+    __shared__ __attribute__((aligned(16))) typename Store<ST>::T pops[W][Q][kTile];
     __shared__ StageLds lds[W / 4];
     const int32_t w = xcd_block((int32_t)blockIdx.x, xcd_group);
-    stream_collide_staged<Q, ST, SC, BRINK, W>(src, dst, tb, n, tiles_alloc, w * W, omega, alpha,
-                                               G, t_next, pops, lds);
+    stream_collide_staged<Q, ST, SC, BRINK, W, DMA>(src, dst, tb, n, tiles_alloc, w * W, omega,
+                                                    alpha, G, t_next, pops, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,15 +324,20 @@ static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* sr
     return dispatch(L.q, L.storage, L.scaled, [&](auto tag) {
         using Tg = decltype(tag);
         using T = typename Store<Tg::ST>::T;
-        if (alpha)
-            k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W><<<(unsigned)grid, W * kTile, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, tiles_alloc,
-                per, omega, alpha, G, t_next);
-        else
-            k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W><<<(unsigned)grid, W * kTile, 0, s>>>(
-                static_cast<const T*>(src), static_cast<T*>(dst), L.tb, (int32_t)L.n, tiles_alloc,
-                per, omega, nullptr, G, t_next);
-        return hipGetLastError();
+        auto go = [&](auto kernel) {
+            kernel<<<(unsigned)grid, W * kTile, 0, s>>>(static_cast<const T*>(src),
+                                                        static_cast<T*>(dst), L.tb, (int32_t)L.n,
+                                                        tiles_alloc, per, omega, alpha, G, t_next);
+            return hipGetLastError();
+        };
+        // the direct-to-LDS copy exists for FP32 rows only
+        if constexpr (Tg::ST == ST_F32) {
+            if (L.lds_dma)
+                return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, true>)
+                             : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, true>);
+        }
+        return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, false>)
+                     : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, false>);
     });
 }
 

@@ -95,6 +95,8 @@ struct Layout {
     // with block addressing and halfway walls: workgroups of this many tiles (4, 8
     // or 16) copy their own populations into LDS first (0: four tiles, no copy)
     int stage_tiles;
+    // FP32 staging copies with loads that write LDS directly
+    bool lds_dma;
 };
 
 // Iolet links, sorted by site then direction.  Link l's incoming population lives

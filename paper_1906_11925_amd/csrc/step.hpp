@@ -212,7 +212,7 @@ __device__ inline void stream_collide_group(const typename Store<ST>::T* __restr
 // staged records of its W/4 groups: every thread takes its share of its group's
 // blob, one barrier, then every wavefront decodes its tile.  Groups whose records
 // did not fit decode from the global records.  Every thread calls it.
-template <int Q, int W>
+template <int Q, int W, bool WAIT_VM = false>
 __device__ inline void links_tiles(const Table& tb, int32_t T0, int32_t n, StageLds (&lds)[W / 4],
                                    int32_t (&j)[Q]) {
     const int wave = (int)threadIdx.x >> kTileShift;
@@ -231,6 +231,9 @@ __device__ inline void links_tiles(const Table& tb, int32_t T0, int32_t n, Stage
                     tb.gblob[h.off + t];
         }
     }
+    // WAIT_VM: the caller issued loads that write LDS directly; they count as vector
+    // memory operations, so wait for every one of them before the barrier
+    if constexpr (WAIT_VM) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (!live) return;
     if (h.nown > 0)
@@ -243,8 +246,10 @@ __device__ inline void links_tiles(const Table& tb, int32_t T0, int32_t n, Stage
 // copies its own tiles' populations into LDS with coalesced loads: a link whose
 // upstream site (or ghost slot) lies in those tiles reads LDS, any other reads
 // global memory, so each wavefront's gathers touch only the lines of tiles outside
-// the workgroup.  Block addressing, halfway walls.  Every thread calls it.
-template <int Q, int ST, bool SC, bool BRINK, int W>
+// the workgroup.  Block addressing, halfway walls.  Every thread calls it.  With DMA
+// (FP32 storage) the copy uses loads that write LDS directly; pops must then be
+// 16-byte aligned.
+template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA = false>
 __device__ inline void stream_collide_staged(const typename Store<ST>::T* __restrict__ src,
                                              typename Store<ST>::T* __restrict__ dst,
                                              const Table& tb, int32_t n, int32_t tiles_alloc,
@@ -258,13 +263,28 @@ __device__ inline void stream_collide_staged(const typename Store<ST>::T* __rest
     if (((int64_t)T0 << kTileShift) >= n) return;
     const int wave = (int)threadIdx.x >> kTileShift, lane = (int)threadIdx.x & (kTile - 1);
     const int32_t staged = min(W, tiles_alloc - T0);  // tiles of the array in this workgroup
+    constexpr bool kDma = DMA && sizeof(T) == 4;
     if (wave < staged) {
-        const int32_t s = ((T0 + wave) << kTileShift) + lane;
+        if constexpr (kDma) {
+            // A tile's Q rows are one contiguous block, in memory as in LDS: copy it
+            // with 16 bytes per lane per load, written straight into LDS (no
+            // registers, no LDS store instructions).  The barrier in links_tiles
+            // waits for these loads.
+            constexpr int kBytes = Q * kTile * 4;
+            const char* g = reinterpret_cast<const char*>(src + (int64_t)(T0 + wave) * (Q * kTile));
+            char* l = reinterpret_cast<char*>(&pops[wave][0][0]);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) pops[wave][i][lane] = src[tix<Q>(i, s)];
+            for (int c = 0; c < (kBytes + 1023) / 1024; ++c)
+                if (c * 1024 + lane * 16 < kBytes)
+                    __builtin_amdgcn_global_load_lds(g + c * 1024 + lane * 16, l + c * 1024, 16, 0, 0);
+        } else {
+            const int32_t s = ((T0 + wave) << kTileShift) + lane;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pops[wave][i][lane] = src[tix<Q>(i, s)];
+        }
     }
     int32_t j[Q];
-    links_tiles<Q, W>(tb, T0, n, lds, j);  // holds the barrier after the staging
+    links_tiles<Q, W, kDma>(tb, T0, n, lds, j);  // holds the barrier after the staging
     const int32_t s = (T0 << kTileShift) + (int32_t)threadIdx.x;
     if (s >= n) return;
     const int32_t lo = T0 << kTileShift;
