@@ -6,8 +6,9 @@ LBGK collide kernel over every fluid site of the workload, whose epilogue also
 writes the next step's incoming iolet populations (site updates counted as in
 the paper's Table 3: sites x steps / wall time).  Default workload: the seeded
 Murray tree in a 2048^3 box (root radius 64, 8 bifurcation generations, seed 5;
-53,020,072 fluid sites), D3Q15, tau 0.6, FP32 storage, inputs resident in HBM.
-Prints one JSON line.
+53,020,072 fluid sites), D3Q15, tau 0.6, FP32 storage, inputs resident in HBM,
+with velocity, pressure and wall shear stress computed every 100 steps inside the
+timed run, as the workload's configuration states.  Prints one JSON line.
 """
 
 import argparse
@@ -404,8 +405,9 @@ def main():
                     help="skip the other forms, error legs, smaller workloads and the adjoint")
     ap.add_argument("--size-matched", action="store_true",
                     help="also time the ~400M-site size-matched tree (tree2048_400M)")
-    ap.add_argument("--obs-every", type=int, default=0,
-                    help="also compute velocity/pressure/WSS every k steps inside the timed run")
+    ap.add_argument("--obs-every", type=int, default=100,
+                    help="compute velocity/pressure/WSS every k steps inside the timed runs of the "
+                         "benchmark's workload, as its configuration states (0: never)")
     ap.add_argument("--addressing", default="auto", choices=["auto", "blocks", "table16", "table32"],
                     help="how the kernels find upstream neighbours (auto: the library's default)")
     ap.add_argument("--adjoint", action="store_true",
@@ -516,14 +518,16 @@ def main():
         forms = {}
         for st in ("f16", "bf16"):
             if st != args.storage:
-                forms[st] = form_timing(make, geom, st, args.steps, args.warmup)
+                forms[st] = form_timing(make, geom, st, args.steps, args.warmup,
+                                        obs_every=args.obs_every)
                 forms[st]["speedup_vs_" + args.storage] = ms_step / forms[st]["ms_per_step"]
                 log(f"[bench] {st}: {forms[st]['GLUPS']:.2f} GLUPS")
         for st in ("f32", "f16"):
             # the addressing forms the default does not pick, for comparison
             for ad in ("blocks", "table16"):
                 key = f"{st}_{ad}"
-                forms[key] = form_timing(make, geom, st, args.steps, args.warmup, ad)
+                forms[key] = form_timing(make, geom, st, args.steps, args.warmup, ad,
+                                         obs_every=args.obs_every)
                 log(f"[bench] {key}: {forms[key]['GLUPS']:.2f} GLUPS")
         if args.lattice == 15:
             # the paper's lattice on the same workload
@@ -549,7 +553,8 @@ def main():
             mk_big = maker(big)
             extra["tree2048_400M"] = {"sites": big.n_sites}
             for st in ("f32", "f16"):
-                extra["tree2048_400M"][st] = form_timing(mk_big, big, st, 200, 20)
+                extra["tree2048_400M"][st] = form_timing(mk_big, big, st, 200, 20,
+                                                         obs_every=args.obs_every)
                 log(f"[bench] tree2048_400M {st}: {extra['tree2048_400M'][st]['GLUPS']:.2f} GLUPS")
             del big, mk_big
         for key, wname in (("adjoint", "aneurysm_half"), ("adjoint_tree1024", "tree1024")):
@@ -580,7 +585,8 @@ def main():
         "config": {"workload": args.workload, "sites": n, "lattice": f"D3Q{args.lattice}",
                    "storage": args.storage, "tau": geom.tau, "collision": "LBGK",
                    "walls": "halfway bounce-back", "addressing": info["addressing_name"],
-                   "iolets": "Ladd velocity inlet + equilibrium pressure outlets"},
+                   "iolets": "Ladd velocity inlet + equilibrium pressure outlets",
+                   "observables_every": args.obs_every},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_update": mb,
