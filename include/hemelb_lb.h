@@ -205,6 +205,18 @@ int hemelb_lb_links(const uint8_t* labels, const int32_t shape[3], const int32_t
  * build the device neighbour table, allocate ping-pong population buffers and
  * set the rest equilibrium at time 0.
  * Errors: EINVAL (message names the first offending site/direction), ENOMEM, EDEVICE.
+ *
+ * Launch-shape settings, read from the environment when a handle is created (none
+ * changes any result bit; each exists to compare kernel forms):
+ *   HEMELB_XCD_GROUP=G     consecutive workgroups given to one XCD (default 16; 0
+ *                          leaves the hardware's round-robin)
+ *   HEMELB_STAGE_TILES=W   tiles per workgroup that copy their own populations into
+ *                          LDS first: 4, 8 or 16, anything else none (default, with
+ *                          block addressing: FP32 8 for D3Q15 from 4M sites, else 4;
+ *                          none below 256 four-tile groups or with 16-bit storage)
+ *   HEMELB_LDS_DMA=0       make that copy go through registers instead of loads
+ *                          that write LDS directly
+ *   HEMELB_VERBOSE=1       print the time of each setup phase to stderr
  */
 int hemelb_lb_create(hemelb_lb_t* out, const hemelb_lb_desc_t* desc);
 
