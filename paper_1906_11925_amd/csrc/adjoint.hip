@@ -244,12 +244,15 @@ __device__ inline void iolet_terms(const typename Store<ST>::T* __restrict__ A, 
 
 // ---------------------------------------------------------------------------
 // one reverse kernel (group grp of four tiles; every thread of the workgroup
-// calls it).  A: taped state of the collision step (ADJ_OWN, ADJ_PULL); Ai: taped
-// state of the stream step (ADJ_PULL, ADJ_FINAL).
+// calls it).  A: taped state of the collision step (ADJ_OWN, ADJ_PULL), whose
+// pre-collision populations f_t the kernel re-gathers, unless F (uniform) holds
+// them already, as the recording forward stored them in the sites' own slots; Ai:
+// taped state of the stream step (ADJ_PULL, ADJ_FINAL).
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool SC, bool BRINK, int MODE>
 __device__ inline void adj_group(
-    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ Ai,
+    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ F,
+    const typename Store<ST>::T* __restrict__ Ai,
     const float* __restrict__ gin, float* __restrict__ gout, const Table& tb, int32_t n,
     float omega, const float* __restrict__ alpha, double* __restrict__ alpha_hat,
     const float* __restrict__ wss_w, const float* __restrict__ normal, const Ghosts& G,
@@ -297,8 +300,14 @@ __device__ inline void adj_group(
         for (int i = 0; i < Q; ++i) gout[tix<Q>(i, s)] = g[i];
         return;
     } else {
+        using C = Codec<Q, ST, SC>;
         float d[Q];
-        gather_pre<Q, ST, SC>(A, s, n, d, j);
+        if (F) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = C::dec(i, F[tix<Q>(i, s)]);
+        } else {
+            gather_pre<Q, ST, SC>(A, s, n, d, j);
+        }
         float drho, mx, my, mz;
         moments<Q>(d, drho, mx, my, mz);
         const float rho = 1.0f + drho;
@@ -359,13 +368,14 @@ __device__ inline void adj_group(
 
 template <int Q, int ST, bool SC, bool BRINK, int MODE>
 __global__ __launch_bounds__(kBlock) void k_adj_step(
-    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ Ai,
+    const typename Store<ST>::T* __restrict__ A, const typename Store<ST>::T* __restrict__ F,
+    const typename Store<ST>::T* __restrict__ Ai,
     const float* __restrict__ gin, float* __restrict__ gout, Table tb, int32_t n,
     int32_t xcd_group, float omega, const float* __restrict__ alpha,
     double* __restrict__ alpha_hat, const float* __restrict__ wss_w,
     const float* __restrict__ normal, Ghosts G, IoletAdj I) {
     __shared__ StageLds lds;
-    adj_group<Q, ST, SC, BRINK, MODE>(A, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
+    adj_group<Q, ST, SC, BRINK, MODE>(A, F, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
                                       normal, G, I, xcd_block((int32_t)blockIdx.x, xcd_group),
                                       lds);
 }
@@ -388,8 +398,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_dual(
     __shared__ StageLds lds[1];
     const int32_t b = (int32_t)blockIdx.x;
     if (b < nb) {
-        adj_group<Q, ST, SC, BRINK, MODE>(A, Ai, gin, gout, tb, n, omega, alpha, alpha_hat, wss_w,
-                                          normal, G, I, xcd_block(b, xcd_group), lds[0]);
+        adj_group<Q, ST, SC, BRINK, MODE>(A, nullptr, Ai, gin, gout, tb, n, omega, alpha,
+                                          alpha_hat, wss_w, normal, G, I, xcd_block(b, xcd_group),
+                                          lds[0]);
         return;
     }
     const int32_t g = xcd_block(b - nb, xcd_group);
@@ -438,33 +449,33 @@ static int64_t adj_grid(int64_t n, int xcd_group) {
 // the kernel for one (mode, Brinkman) choice, as a function of the dispatch tag
 template <int MODE, bool BRINK, typename Tg>
 static hipError_t adj_step_mode(const Layout& L, const Ghosts& G, const IoletAdj& I,
-                                const void* A, const void* Ai, const float* gin, float* gout,
+                                const void* A, const void* F, const void* Ai, const float* gin, float* gout,
                                 float omega, const float* alpha, double* alpha_hat,
                                 const float* wss_w, const float* normal, int xcd_group,
                                 hipStream_t s) {
     using T = typename Store<Tg::ST>::T;
     k_adj_step<Tg::Q, Tg::ST, Tg::SC, BRINK, MODE>
         <<<(unsigned)adj_grid(L.n, xcd_group), kBlock, 0, s>>>(
-            static_cast<const T*>(A), static_cast<const T*>(Ai), gin, gout, L.tb, (int32_t)L.n,
-            xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
+            static_cast<const T*>(A), static_cast<const T*>(F), static_cast<const T*>(Ai), gin, gout,
+            L.tb, (int32_t)L.n, xcd_group, omega, alpha, alpha_hat, wss_w, normal, G, I);
     return hipGetLastError();
 }
 
 template <int MODE, typename Tg>
 static hipError_t adj_step_brink(const Layout& L, const Ghosts& G, const IoletAdj& I,
-                                 const void* A, const void* Ai, const float* gin, float* gout,
+                                 const void* A, const void* F, const void* Ai, const float* gin, float* gout,
                                  float omega, const float* alpha, double* alpha_hat,
                                  const float* wss_w, const float* normal, int xcd_group,
                                  hipStream_t s) {
     if (alpha && MODE != ADJ_FINAL)
-        return adj_step_mode<MODE, true, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha, alpha_hat,
+        return adj_step_mode<MODE, true, Tg>(L, G, I, A, F, Ai, gin, gout, omega, alpha, alpha_hat,
                                              wss_w, normal, xcd_group, s);
-    return adj_step_mode<MODE, false, Tg>(L, G, I, A, Ai, gin, gout, omega, nullptr, alpha_hat,
+    return adj_step_mode<MODE, false, Tg>(L, G, I, A, F, Ai, gin, gout, omega, nullptr, alpha_hat,
                                           wss_w, normal, xcd_group, s);
 }
 
 hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, int mode,
-                           const void* A, const void* Ai, const float* gin, float* gout,
+                           const void* A, const void* F, const void* Ai, const float* gin, float* gout,
                            float omega, const float* alpha, double* alpha_hat,
                            const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s) {
@@ -473,13 +484,13 @@ hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, 
         using Tg = decltype(tag);
         switch (mode) {
             case ADJ_OWN:
-                return adj_step_brink<ADJ_OWN, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha,
+                return adj_step_brink<ADJ_OWN, Tg>(L, G, I, A, F, Ai, gin, gout, omega, alpha,
                                                    alpha_hat, wss_w, normal, xcd_group, s);
             case ADJ_PULL:
-                return adj_step_brink<ADJ_PULL, Tg>(L, G, I, A, Ai, gin, gout, omega, alpha,
+                return adj_step_brink<ADJ_PULL, Tg>(L, G, I, A, F, Ai, gin, gout, omega, alpha,
                                                     alpha_hat, wss_w, normal, xcd_group, s);
             case ADJ_FINAL:
-                return adj_step_brink<ADJ_FINAL, Tg>(L, G, I, A, Ai, gin, gout, omega, nullptr,
+                return adj_step_brink<ADJ_FINAL, Tg>(L, G, I, A, F, Ai, gin, gout, omega, nullptr,
                                                      nullptr, nullptr, normal, xcd_group, s);
         }
         return hipErrorInvalidValue;

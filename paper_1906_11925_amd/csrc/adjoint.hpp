@@ -51,7 +51,9 @@ struct IoletAdj {
 // it holds ghat_t = dJ/dA_t.  Every kernel writes only its own sites' rows
 // (coalesced), so nothing is scattered and nothing waits for another thread.
 //   ADJ_OWN   ghat_{t+1} (gin, own rows) -> fhat_t: the transposed collision of step
-//             t at the taped state A (= A_t), the wall-shear term, dJ/dalpha.
+//             t at the taped state A (= A_t), the wall-shear term, dJ/dalpha.  F
+//             (optional): the pre-collision populations f_t in the sites' own slots,
+//             as the recording forward stored them; then A is not read.
 //   ADJ_PULL  fhat_{t+1} (gin) -> fhat_t: first ghat_{t+1} by the stream transpose
 //             of step t + 1 (population k of site s was read by the link of the
 //             site s + c_k, i.e. by the link opp(k) of s pulling the other way, by
@@ -65,8 +67,8 @@ enum AdjMode { ADJ_OWN = 0, ADJ_PULL = 1, ADJ_FINAL = 2 };
 // wss_w: per-site weight of the wall-shear term of step t, or null outside the
 // window; xcd_group: the workgroup-to-XCD grouping of the forward step.
 hipError_t launch_adj_step(const Layout& L, const Ghosts& G, const IoletAdj& I, int mode,
-                           const void* A, const void* Ai, const float* gin, float* gout,
-                           float omega, const float* alpha, double* alpha_hat,
+                           const void* A, const void* F, const void* Ai, const float* gin,
+                           float* gout, float omega, const float* alpha, double* alpha_hat,
                            const float* wss_w, const float* normal, int xcd_group,
                            hipStream_t s);
 

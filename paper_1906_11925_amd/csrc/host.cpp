@@ -311,8 +311,10 @@ struct hemelb_lb {
     std::vector<void*> tape;  // K+1 population buffers of a recompute segment
     std::vector<void*> tape2;  // a second tape: recompute one segment while reversing another
     // recorded trajectory: rec[m] holds the state at time rec_t0 + m; while recording,
-    // A[] point into rec and the handle's own population buffers wait in A_own
-    std::vector<void*> rec;
+    // A[] point into rec and the handle's own population buffers wait in A_own.  With
+    // FP32 storage (halfway walls) frec[m] holds the pre-collision populations of step
+    // rec_t0 + m, which the reverse sweep then reads in place instead of re-gathering.
+    std::vector<void*> rec, frec;
     int64_t rec_t0 = -1;
     void* A_own[2] = {nullptr, nullptr};
     struct Series {            // iolet values and Fourier basis of one segment
@@ -386,6 +388,8 @@ void release(hemelb_lb* h) {
         h->A[1] = h->A_own[1];
     }
     for (void* p : h->rec)
+        if (p) (void)hipFree(p);
+    for (void* p : h->frec)
         if (p) (void)hipFree(p);
     void* ptrs[] = {h->A[0],      h->A[1],      h->tbl,        h->g_site,    h->g_dir,
                     h->t16,       h->toff,      h->tlist,      h->brec,      h->gmask,
@@ -822,12 +826,14 @@ int fill_series(hemelb_lb* h, int64_t t0, int64_t count) {
 
 int do_step(hemelb_lb* h) {
     const hlb::Layout L = h->layout();
+    void* fout = nullptr;
     if (h->rec_t0 >= 0) {  // recording: the new state goes to the next recorded buffer
         const int64_t m = h->t - h->rec_t0;
         if (m + 1 >= (int64_t)h->rec.size())
             return fail(HEMELB_EORDER, "the record holds %lld steps; end it before stepping on",
                         (long long)h->rec.size() - 1);
         h->A[h->cur ^ 1] = h->rec[m + 1];
+        if (m < (int64_t)h->frec.size()) fout = h->frec[m];
     }
     void* src = h->A[h->cur];
     void* dst = h->A[h->cur ^ 1];
@@ -843,7 +849,7 @@ int do_step(hemelb_lb* h) {
     const bool timed = h->ev_used + 2 <= (int64_t)h->ev.size() && h->ev_cap > 0;
     if (timed) HIP_TRY(hipEventRecord(h->ev[h->ev_used], h->stream), "event");
     HIP_TRY(hlb::launch_stream_collide(L, h->ghosts(), src, dst, h->omega, h->alpha, h->xcd_group,
-                                       h->t + 1, h->stream),
+                                       h->t + 1, h->stream, fout),
             "stream collide");
     if (timed) {
         HIP_TRY(hipEventRecord(h->ev[h->ev_used + 1], h->stream), "event");
@@ -1279,17 +1285,19 @@ const float* wss_weights(const hemelb_lb* h, int64_t t) {
     return t >= h->w0 && t < h->w1 ? h->d_wss_w : nullptr;
 }
 
-// Reverse kernel of step t0 + m of a segment of `steps` steps (tape[m] = A_{t0+m}):
-// the segment's last step starts from dJ/dA_{t0+steps}, the others from the fhat
-// of the step after.
+// Reverse kernel of step t0 + m of a segment of `steps` steps (tape[m] = A_{t0+m};
+// ftape, if given, holds the steps' pre-collision populations): the segment's last
+// step starts from dJ/dA_{t0+steps}, the others from the fhat of the step after.
 int reverse_mode(int64_t m, int64_t steps) { return m == steps - 1 ? hlb::ADJ_OWN : hlb::ADJ_PULL; }
 
-int reverse_step(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
-                 int64_t m, int64_t steps, hipStream_t stream) {
+int reverse_step(hemelb_lb* h, std::vector<void*>& tape, const std::vector<void*>* ftape,
+                 const hemelb_lb::Series& sr, int64_t t0, int64_t m, int64_t steps,
+                 hipStream_t stream) {
     const int64_t t = t0 + m;
     const int mode = reverse_mode(m, steps);
+    const void* F = ftape ? (*ftape)[m] : nullptr;
     HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t + 1), mode,
-                                 tape[m], tape[m + 1], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
+                                 tape[m], F, tape[m + 1], h->ghat[h->gcur], h->ghat[h->gcur ^ 1],
                                  h->omega, h->alpha, h->alpha_hat, wss_weights(h, t), h->normal,
                                  h->xcd_group, stream),
             "adjoint step");
@@ -1322,7 +1330,7 @@ int dual_step(hemelb_lb* h, std::vector<void*>& tf, const hemelb_lb::Series& sf,
 int end_reverse(hemelb_lb* h, std::vector<void*>& tape, const hemelb_lb::Series& sr, int64_t t0,
                 hipStream_t stream) {
     HIP_TRY(hlb::launch_adj_step(h->layout(), segment_ghosts(h, sr), iolet_adj(h, t0),
-                                 hlb::ADJ_FINAL, nullptr, tape[0], h->ghat[h->gcur],
+                                 hlb::ADJ_FINAL, nullptr, nullptr, tape[0], h->ghat[h->gcur],
                                  h->ghat[h->gcur ^ 1], h->omega, nullptr, nullptr, nullptr,
                                  h->normal, h->xcd_group, stream),
             "adjoint segment end");
@@ -2119,7 +2127,7 @@ static int adjoint_segment_impl(hemelb_lb_t h, const void* checkpoint, int64_t t
     int rc = begin_recompute(h, h->tape, h->series[0], checkpoint, t0, steps, h->stream);
     for (int64_t m = 0; m < steps && !rc; ++m) rc = recompute_step(h, h->tape, h->series[0], t0, m, h->stream);
     for (int64_t m = steps - 1; m >= 0 && !rc; --m)
-        rc = reverse_step(h, h->tape, h->series[0], t0, m, steps, h->stream);
+        rc = reverse_step(h, h->tape, nullptr, h->series[0], t0, m, steps, h->stream);
     if (!rc) rc = end_reverse(h, h->tape, h->series[0], t0, h->stream);
     if (rc) return rc;
     h->adj_t = t0;
@@ -2183,7 +2191,7 @@ static int adjoint_run_impl(hemelb_lb_t h, const void* const* checkpoints, const
                 rc = dual_step(h, tf, h->series[nb], t0[k - 1], m, tr, h->series[b], t0[k], mr,
                                steps[k], h->stream);
             else if (m < steps[k])
-                rc = reverse_step(h, tr, h->series[b], t0[k], mr, steps[k], h->stream);
+                rc = reverse_step(h, tr, nullptr, h->series[b], t0[k], mr, steps[k], h->stream);
             else
                 rc = recompute_step(h, tf, h->series[nb], t0[k - 1], m, h->stream);
             if (rc) return rc;
@@ -2206,21 +2214,27 @@ static int record_impl(hemelb_lb_t h, int64_t max_steps) {
     if (h->rec_t0 >= 0) return fail(HEMELB_EORDER, "a trajectory is already being recorded");
     HIP_TRY(hipSetDevice(h->device), "set device");
     const size_t popbytes = (size_t)h->q * h->slots * h->elem();
-    std::vector<void*> rec;
-    for (int64_t m = 0; m <= max_steps; ++m) {
+    // max_steps + 1 states and, with FP32 storage and halfway walls, the pre-collision
+    // populations of each recorded step (with 16-bit storage the reverse step's
+    // re-gather is as fast as reading them, so they are not kept)
+    std::vector<void*> rec, frec;
+    const int64_t nf = h->storage == HEMELB_STORE_F32 && !h->bfl ? max_steps : 0;
+    for (int64_t m = 0; m <= max_steps + nf; ++m) {
         void* p = nullptr;
         const hipError_t e = hipMalloc(&p, popbytes);
         if (e != hipSuccess) {
             for (void* x : rec) (void)hipFree(x);
+            for (void* x : frec) (void)hipFree(x);
             return hip_fail(e, "trajectory record");
         }
-        rec.push_back(p);
+        (m <= max_steps ? rec : frec).push_back(p);
     }
     // the current state (with its ghost slots) starts the record
     HIP_TRY(hipMemcpyAsync(rec[0], h->A[h->cur], popbytes, hipMemcpyDeviceToDevice, h->stream),
             "record start");
     h->rec = std::move(rec);
-    h->device_bytes += (int64_t)(popbytes * h->rec.size());
+    h->frec = std::move(frec);
+    h->device_bytes += (int64_t)(popbytes * (h->rec.size() + h->frec.size()));
     h->A_own[0] = h->A[0];
     h->A_own[1] = h->A[1];
     h->A[h->cur] = h->rec[0];
@@ -2250,8 +2264,10 @@ int hemelb_lb_record_end(hemelb_lb_t h) {
     h->A[0] = h->A_own[0];
     h->A[1] = h->A_own[1];
     for (void* p : h->rec) (void)hipFree(p);
-    h->device_bytes -= (int64_t)(popbytes * h->rec.size());
+    for (void* p : h->frec) (void)hipFree(p);
+    h->device_bytes -= (int64_t)(popbytes * (h->rec.size() + h->frec.size()));
     h->rec.clear();
+    h->frec.clear();
     h->rec_t0 = -1;
     return HEMELB_OK;
 }
@@ -2268,7 +2284,8 @@ static int adjoint_recorded_impl(hemelb_lb_t h) {
     h->ghosts_ready = false;
     int rc = fill_segment_series(h, h->series[0], h->rec_t0, steps + 1, h->stream);
     for (int64_t m = steps - 1; m >= 0 && !rc; --m)
-        rc = reverse_step(h, h->rec, h->series[0], h->rec_t0, m, steps, h->stream);
+        rc = reverse_step(h, h->rec, h->frec.empty() ? nullptr : &h->frec, h->series[0],
+                          h->rec_t0, m, steps, h->stream);
     if (!rc) rc = end_reverse(h, h->rec, h->series[0], h->rec_t0, h->stream);
     if (rc) return rc;
     h->adj_t = h->rec_t0;

@@ -43,11 +43,11 @@ template <int Q, int ST, bool SC, bool BRINK, bool BFL>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha, Ghosts G,
-    int64_t t_next) {
+    int64_t t_next, typename Store<ST>::T* __restrict__ fout) {
     __shared__ StageLds lds;
     stream_collide_group<Q, ST, SC, BRINK, BFL>(src, dst, tb, n,
                                                 xcd_block((int32_t)blockIdx.x, xcd_group), omega,
-                                                alpha, G, t_next, lds);
+                                                alpha, G, t_next, lds, fout);
 }
 
 // workgroups of W tiles with their own populations staged in LDS (block addressing);
@@ -56,12 +56,13 @@ template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA>
 __global__ __launch_bounds__(W * kTile) void k_stream_collide_staged(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t tiles_alloc, int32_t xcd_group, float omega,
-    const float* __restrict__ alpha, Ghosts G, int64_t t_next) {
+    const float* __restrict__ alpha, Ghosts G, int64_t t_next,
+    typename Store<ST>::T* __restrict__ fout) {
     __shared__ __attribute__((aligned(16))) typename Store<ST>::T pops[W][Q][kTile];
     __shared__ StageLds lds[W / 4];
     const int32_t w = xcd_block((int32_t)blockIdx.x, xcd_group);
     stream_collide_staged<Q, ST, SC, BRINK, W, DMA>(src, dst, tb, n, tiles_alloc, w * W, omega,
-                                                    alpha, G, t_next, pops, lds);
+                                                    alpha, G, t_next, pops, lds, fout);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,7 +314,7 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
 template <int W>
 static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* src, void* dst,
                                 float omega, const float* alpha, int xcd_group, int64_t t_next,
-                                hipStream_t s) {
+                                void* fout, hipStream_t s) {
     const int64_t tiles = (L.n + kTile - 1) / kTile;
     const int64_t nb = (tiles + W - 1) / W;
     // the same number of tiles per XCD chunk as the four-tile workgroups
@@ -327,7 +328,8 @@ static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* sr
         auto go = [&](auto kernel) {
             kernel<<<(unsigned)grid, W * kTile, 0, s>>>(static_cast<const T*>(src),
                                                         static_cast<T*>(dst), L.tb, (int32_t)L.n,
-                                                        tiles_alloc, per, omega, alpha, G, t_next);
+                                                        tiles_alloc, per, omega, alpha, G, t_next,
+                                                        static_cast<T*>(fout));
             return hipGetLastError();
         };
         // the direct-to-LDS copy exists for FP32 rows only
@@ -343,12 +345,13 @@ static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* sr
 
 hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* src, void* dst,
                                  float omega, const float* alpha, int xcd_group, int64_t t_next,
-                                 hipStream_t s) {
+                                 hipStream_t s, void* fout) {
     if (L.n == 0) return hipSuccess;
+    if (fout && L.bfl) return hipErrorInvalidValue;  // interpolated values are not stored values
     if (L.stage_tiles > 0 && L.tb.grp && !L.bfl) {
-        if (L.stage_tiles == 4) return launch_staged<4>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
-        if (L.stage_tiles == 8) return launch_staged<8>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
-        if (L.stage_tiles == 16) return launch_staged<16>(L, G, src, dst, omega, alpha, xcd_group, t_next, s);
+        if (L.stage_tiles == 4) return launch_staged<4>(L, G, src, dst, omega, alpha, xcd_group, t_next, fout, s);
+        if (L.stage_tiles == 8) return launch_staged<8>(L, G, src, dst, omega, alpha, xcd_group, t_next, fout, s);
+        if (L.stage_tiles == 16) return launch_staged<16>(L, G, src, dst, omega, alpha, xcd_group, t_next, fout, s);
     }
     int64_t nb = (L.n + kScBlock - 1) / kScBlock;
     const int32_t per = xcd_group > 0 ? xcd_group : 0;
@@ -360,7 +363,8 @@ hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* s
         auto go = [&](auto kernel, const float* a) {
             kernel<<<(unsigned)grid, kScBlock, 0, s>>>(static_cast<const T*>(src),
                                                        static_cast<T*>(dst), L.tb, (int32_t)L.n,
-                                                       per, omega, a, G, t_next);
+                                                       per, omega, a, G, t_next,
+                                                       static_cast<T*>(fout));
         };
         if (alpha)
             L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, true>, alpha)

@@ -118,13 +118,21 @@ __device__ inline void site_pull(const typename Store<ST>::T* __restrict__ src, 
 
 // Collide the pulled populations of site s and store them (and, with the fused
 // ghost epilogue, the incoming populations of its iolet links for time t_next).
+// fout (uniform, usually null): also store the pulled populations themselves, in
+// the site's own slots, for the reverse sweep (exact: each is a stored value
+// decoded; halfway walls only).
 template <int Q, int ST, bool SC, bool BRINK>
 __device__ inline void site_collide_store(typename Store<ST>::T* __restrict__ dst, int32_t n,
                                           float omega, const float* __restrict__ alpha,
                                           const Ghosts& G, int64_t t_next, int32_t s,
-                                          const Pulled<Q>& P) {
+                                          const Pulled<Q>& P,
+                                          typename Store<ST>::T* __restrict__ fout) {
     using C = Codec<Q, ST, SC>;
     const float(&d)[Q] = P.d;
+    if (fout) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) st_pop(fout + tix<Q>(i, s), C::enc(i, d[i]));
+    }
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
     const float rho = 1.0f + drho;
@@ -172,10 +180,11 @@ template <int Q, int ST, bool SC, bool BRINK, bool BFL>
 __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
                                    typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
                                    const float* __restrict__ alpha, const Ghosts& G,
-                                   int64_t t_next, int32_t s, const int32_t (&j)[Q]) {
+                                   int64_t t_next, int32_t s, const int32_t (&j)[Q],
+                                   typename Store<ST>::T* __restrict__ fout) {
     Pulled<Q> P;
     site_pull<Q, ST, SC, BFL>(src, n, G, s, j, P);
-    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P);
+    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P, fout);
 }
 
 // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
@@ -197,7 +206,8 @@ __device__ inline void stream_collide_group(const typename Store<ST>::T* __restr
                                             typename Store<ST>::T* __restrict__ dst,
                                             const Table& tb, int32_t n, int32_t g, float omega,
                                             const float* __restrict__ alpha, const Ghosts& G,
-                                            int64_t t_next, StageLds& lds) {
+                                            int64_t t_next, StageLds& lds,
+                                            typename Store<ST>::T* __restrict__ fout = nullptr) {
     if (g * kScBlock >= n) return;  // the whole workgroup lies past the end
     const int32_t s = g * kScBlock + (int32_t)threadIdx.x;
     const bool live = (s & ~(kTile - 1)) < n;  // the wavefront's tile has sites
@@ -205,7 +215,7 @@ __device__ inline void stream_collide_group(const typename Store<ST>::T* __restr
     int32_t j[Q];
     links_group<Q, HLB_NT_TABLE != 0>(tb, g, s, live, lds, j);
     if (!live || s >= n) return;
-    site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j);
+    site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j, fout);
 }
 
 // Links of the sites of a workgroup of W tiles (W a multiple of 4) from the
@@ -257,7 +267,8 @@ __device__ inline void stream_collide_staged(const typename Store<ST>::T* __rest
                                              const float* __restrict__ alpha, const Ghosts& G,
                                              int64_t t_next,
                                              typename Store<ST>::T (&pops)[W][Q][kTile],
-                                             StageLds (&lds)[W / 4]) {
+                                             StageLds (&lds)[W / 4],
+                                             typename Store<ST>::T* __restrict__ fout = nullptr) {
     using T = typename Store<ST>::T;
     using C = Codec<Q, ST, SC>;
     if (((int64_t)T0 << kTileShift) >= n) return;
@@ -315,7 +326,7 @@ __device__ inline void stream_collide_staged(const typename Store<ST>::T* __rest
             }
     }
 #endif
-    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P);
+    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P, fout);
 }
 
 }  // namespace hlb

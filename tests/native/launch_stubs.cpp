@@ -15,7 +15,7 @@ hipError_t launch_ghost_fill(const Layout&, const Ghosts&, void*, int64_t, hipSt
     return hipErrorNoDevice;
 }
 hipError_t launch_stream_collide(const Layout&, const Ghosts&, const void*, void*, float,
-                                 const float*, int, int64_t, hipStream_t) {
+                                 const float*, int, int64_t, hipStream_t, void*) {
     return hipErrorNoDevice;
 }
 bool ghosts_fused() { return true; }
@@ -48,8 +48,8 @@ hipError_t launch_objective(const Layout&, const Ghosts&, const void*, const Obj
     return hipErrorNoDevice;
 }
 hipError_t launch_adj_step(const Layout&, const Ghosts&, const IoletAdj&, int, const void*,
-                           const void*, const float*, float*, float, const float*, double*,
-                           const float*, const float*, int, hipStream_t) {
+                           const void*, const void*, const float*, float*, float, const float*,
+                           double*, const float*, const float*, int, hipStream_t) {
     return hipErrorNoDevice;
 }
 hipError_t launch_adj_dual(const Layout&, const Ghosts&, const void*, void*, int64_t,
