@@ -39,20 +39,20 @@
 
 namespace hlb {
 
-template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+template <int Q, int ST, bool SC, bool BRINK, bool BFL, bool FOUT>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t xcd_group, float omega, const float* __restrict__ alpha, Ghosts G,
     int64_t t_next, typename Store<ST>::T* __restrict__ fout) {
     __shared__ StageLds lds;
-    stream_collide_group<Q, ST, SC, BRINK, BFL>(src, dst, tb, n,
-                                                xcd_block((int32_t)blockIdx.x, xcd_group), omega,
-                                                alpha, G, t_next, lds, fout);
+    stream_collide_group<Q, ST, SC, BRINK, BFL, FOUT>(src, dst, tb, n,
+                                                      xcd_block((int32_t)blockIdx.x, xcd_group),
+                                                      omega, alpha, G, t_next, lds, fout);
 }
 
 // workgroups of W tiles with their own populations staged in LDS (block addressing);
-// DMA: the copy writes LDS directly (FP32)
-template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA>
+// DMA: the copy writes LDS directly (FP32); FOUT: also store the pulled populations
+template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA, bool FOUT>
 __global__ __launch_bounds__(W * kTile) void k_stream_collide_staged(
     const typename Store<ST>::T* __restrict__ src, typename Store<ST>::T* __restrict__ dst,
     Table tb, int32_t n, int32_t tiles_alloc, int32_t xcd_group, float omega,
@@ -61,8 +61,8 @@ __global__ __launch_bounds__(W * kTile) void k_stream_collide_staged(
     __shared__ __attribute__((aligned(16))) typename Store<ST>::T pops[W][Q][kTile];
     __shared__ StageLds lds[W / 4];
     const int32_t w = xcd_block((int32_t)blockIdx.x, xcd_group);
-    stream_collide_staged<Q, ST, SC, BRINK, W, DMA>(src, dst, tb, n, tiles_alloc, w * W, omega,
-                                                    alpha, G, t_next, pops, lds, fout);
+    stream_collide_staged<Q, ST, SC, BRINK, W, DMA, FOUT>(src, dst, tb, n, tiles_alloc, w * W,
+                                                          omega, alpha, G, t_next, pops, lds, fout);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,14 +332,22 @@ static hipError_t launch_staged(const Layout& L, const Ghosts& G, const void* sr
                                                         static_cast<T*>(fout));
             return hipGetLastError();
         };
-        // the direct-to-LDS copy exists for FP32 rows only
+        // the direct-to-LDS copy exists for FP32 rows only, and so does the store of
+        // the pulled populations (the recording forward)
         if constexpr (Tg::ST == ST_F32) {
+            if (fout)
+                return L.lds_dma
+                           ? (alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, true, true>)
+                                    : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, true, true>))
+                           : (alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, false, true>)
+                                    : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, false, true>));
             if (L.lds_dma)
-                return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, true>)
-                             : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, true>);
+                return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, true, false>)
+                             : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, true, false>);
         }
-        return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, false>)
-                     : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, false>);
+        if (fout) return hipErrorInvalidValue;
+        return alpha ? go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, true, W, false, false>)
+                     : go(k_stream_collide_staged<Tg::Q, Tg::ST, Tg::SC, false, W, false, false>);
     });
 }
 
@@ -366,12 +374,20 @@ hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* s
                                                        per, omega, a, G, t_next,
                                                        static_cast<T*>(fout));
         };
+        if (fout) {  // the recording forward: FP32 storage, halfway walls
+            if constexpr (Tg::ST == ST_F32) {
+                alpha ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, false, true>, alpha)
+                      : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, false, true>, nullptr);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
         if (alpha)
-            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, true>, alpha)
-                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, false>, alpha);
+            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, true, false>, alpha)
+                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, true, false, false>, alpha);
         else
-            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, true>, nullptr)
-                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, false>, nullptr);
+            L.bfl ? go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, true, false>, nullptr)
+                  : go(k_stream_collide<Tg::Q, Tg::ST, Tg::SC, false, false, false>, nullptr);
         return hipGetLastError();
     });
 }

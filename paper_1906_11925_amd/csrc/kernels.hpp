@@ -134,9 +134,9 @@ hipError_t launch_ghost_fill(const Layout& L, const Ghosts& G, void* A, int64_t 
 
 // xcd_group: consecutive workgroups per XCD in the workgroup-to-tile mapping (0:
 // identity).  When ghosts_fused(), the kernel also fills dst's ghost slots for
-// time t_next.  fout (optional, same layout and storage as dst): also receives the
-// step's pre-collision populations f, for the reverse sweep (not with interpolated
-// walls: hipErrorInvalidValue).
+// time t_next.  fout (optional, same layout and storage as dst; FP32 storage and
+// halfway walls only, else hipErrorInvalidValue): also receives the step's
+// pre-collision populations f, for the reverse sweep.
 hipError_t launch_stream_collide(const Layout& L, const Ghosts& G, const void* src, void* dst,
                                  float omega, const float* alpha, int xcd_group, int64_t t_next,
                                  hipStream_t s, void* fout = nullptr);

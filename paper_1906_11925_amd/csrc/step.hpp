@@ -118,10 +118,10 @@ __device__ inline void site_pull(const typename Store<ST>::T* __restrict__ src, 
 
 // Collide the pulled populations of site s and store them (and, with the fused
 // ghost epilogue, the incoming populations of its iolet links for time t_next).
-// fout (uniform, usually null): also store the pulled populations themselves, in
-// the site's own slots, for the reverse sweep (exact: each is a stored value
-// decoded; halfway walls only).
-template <int Q, int ST, bool SC, bool BRINK>
+// FOUT: also store the pulled populations themselves into fout, in the site's own
+// slots, for the reverse sweep (exact: each is a stored value decoded; halfway
+// walls only).
+template <int Q, int ST, bool SC, bool BRINK, bool FOUT = false>
 __device__ inline void site_collide_store(typename Store<ST>::T* __restrict__ dst, int32_t n,
                                           float omega, const float* __restrict__ alpha,
                                           const Ghosts& G, int64_t t_next, int32_t s,
@@ -129,9 +129,11 @@ __device__ inline void site_collide_store(typename Store<ST>::T* __restrict__ ds
                                           typename Store<ST>::T* __restrict__ fout) {
     using C = Codec<Q, ST, SC>;
     const float(&d)[Q] = P.d;
-    if (fout) {
+    if constexpr (FOUT) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) st_pop(fout + tix<Q>(i, s), C::enc(i, d[i]));
+    } else {
+        (void)fout;
     }
     float drho, mx, my, mz;
     moments<Q>(d, drho, mx, my, mz);
@@ -176,7 +178,7 @@ __device__ inline void site_collide_store(typename Store<ST>::T* __restrict__ ds
 }
 
 // Pull, collide and store one site whose links are decoded in j.
-template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+template <int Q, int ST, bool SC, bool BRINK, bool BFL, bool FOUT = false>
 __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src,
                                    typename Store<ST>::T* __restrict__ dst, int32_t n, float omega,
                                    const float* __restrict__ alpha, const Ghosts& G,
@@ -184,7 +186,7 @@ __device__ inline void site_update(const typename Store<ST>::T* __restrict__ src
                                    typename Store<ST>::T* __restrict__ fout) {
     Pulled<Q> P;
     site_pull<Q, ST, SC, BFL>(src, n, G, s, j, P);
-    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P, fout);
+    site_collide_store<Q, ST, SC, BRINK, FOUT>(dst, n, omega, alpha, G, t_next, s, P, fout);
 }
 
 // Block ids are dealt round-robin to the 8 XCDs (each with its own L2).  With
@@ -200,8 +202,8 @@ __device__ inline int32_t xcd_block(int32_t b, int32_t xcd_group) {
 }
 
 // One workgroup (group g of four tiles) of the fused step.  Every thread of the
-// workgroup calls it.
-template <int Q, int ST, bool SC, bool BRINK, bool BFL>
+// workgroup calls it.  FOUT: also store the pulled populations into fout.
+template <int Q, int ST, bool SC, bool BRINK, bool BFL, bool FOUT = false>
 __device__ inline void stream_collide_group(const typename Store<ST>::T* __restrict__ src,
                                             typename Store<ST>::T* __restrict__ dst,
                                             const Table& tb, int32_t n, int32_t g, float omega,
@@ -215,7 +217,7 @@ __device__ inline void stream_collide_group(const typename Store<ST>::T* __restr
     int32_t j[Q];
     links_group<Q, HLB_NT_TABLE != 0>(tb, g, s, live, lds, j);
     if (!live || s >= n) return;
-    site_update<Q, ST, SC, BRINK, BFL>(src, dst, n, omega, alpha, G, t_next, s, j, fout);
+    site_update<Q, ST, SC, BRINK, BFL, FOUT>(src, dst, n, omega, alpha, G, t_next, s, j, fout);
 }
 
 // Links of the sites of a workgroup of W tiles (W a multiple of 4) from the
@@ -259,7 +261,7 @@ __device__ inline void links_tiles(const Table& tb, int32_t T0, int32_t n, Stage
 // the workgroup.  Block addressing, halfway walls.  Every thread calls it.  With DMA
 // (FP32 storage) the copy uses loads that write LDS directly; pops must then be
 // 16-byte aligned.
-template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA = false>
+template <int Q, int ST, bool SC, bool BRINK, int W, bool DMA = false, bool FOUT = false>
 __device__ inline void stream_collide_staged(const typename Store<ST>::T* __restrict__ src,
                                              typename Store<ST>::T* __restrict__ dst,
                                              const Table& tb, int32_t n, int32_t tiles_alloc,
@@ -326,7 +328,7 @@ __device__ inline void stream_collide_staged(const typename Store<ST>::T* __rest
             }
     }
 #endif
-    site_collide_store<Q, ST, SC, BRINK>(dst, n, omega, alpha, G, t_next, s, P, fout);
+    site_collide_store<Q, ST, SC, BRINK, FOUT>(dst, n, omega, alpha, G, t_next, s, P, fout);
 }
 
 }  // namespace hlb
