@@ -199,16 +199,22 @@ def test_16bit_storage_gradients(tiny, storage):
     assert et <= bound and ea <= bound
 
 
-def _gpu_run_recorded(P):
+def _gpu_run_recorded(P, storage="f32", record_bytes=None):
     """Forward with every state kept on the device, then the reverse sweep over
-    them without recomputation."""
+    them without recomputation.  record_bytes (a list): receives the device bytes
+    the record added."""
     g, obj = P["g"], P["obj"]
-    lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32))
+    lb = LB.from_geometry(g, lattice=P["lattice"], alpha=P["alpha"].astype(np.float32),
+                          storage=storage)
     lb.set_objective(obj.outlet, obj.q_target, obj.dome, obj.lam, obj.window)
     if P["d0"] is not None:
         lb.set_deviations(torch.from_numpy(P["d0"]), t=0)
     T = P["T"]
+    before = lb.info()["device_bytes"]
     lb.record(T)
+    if record_bytes is not None:
+        info = lb.info()
+        record_bytes.append((info["device_bytes"] - before, info["pitch"]))
     lb.step(T)
     J = lb.objective_value()
     q = lb.objective_flux()
@@ -231,6 +237,26 @@ def test_recorded_sweep_is_bit_identical(tiny):
     for x, y in zip(a[1:], b[1:]):
         assert np.array_equal(np.asarray(x), np.asarray(y))
     assert _rel(a[2], tiny["theta"]) <= 1e-4 and _rel(a[3], tiny["ahat"]) <= 1e-4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_recorded_sweep_in_every_storage(tiny, storage):
+    """The recorded sweep gives the checkpointed sweep's bits in every storage.
+    With FP32 storage the record also keeps each step's pre-collision populations
+    (T more buffers), which the reverse step reads instead of re-gathering; with
+    16-bit storage it keeps the T + 1 states only."""
+    _gpu()
+    got = []
+    a = _gpu_run_recorded(tiny, storage, got)
+    b = _gpu_run(tiny, 7, pipelined=True, storage=storage)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    T, q = tiny["T"], tiny["lattice"]
+    added, pitch = got[0]
+    elem = 4 if storage == "f32" else 2
+    buffers = 2 * T + 1 if storage == "f32" else T + 1
+    assert added == buffers * q * pitch * elem
 
 
 def test_recording_keeps_the_forward_and_its_rules(tiny):
