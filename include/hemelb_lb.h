@@ -475,11 +475,12 @@ int hemelb_lb_adjoint_run(hemelb_lb_t h, const void* const* checkpoints, const i
  * allocates max_steps + 1 population buffers and copies the current state (time
  * t0) into the first; each following step writes its new state into the next
  * buffer instead of the handle's own, so the trajectory t0 .. t0 + max_steps
- * stays on the device.  With FP32 storage and halfway walls it allocates max_steps
- * more buffers, into which each recorded step also stores its pre-collision
- * populations, so that the reverse sweep reads them instead of re-gathering them
- * (4000 steps of the 199k-site half aneurysm in FP32: 96 GB in all; with 16-bit
- * storage only the states are kept).  Every other call works as before; a
+ * stays on the device.  With FP32 storage and halfway walls it also allocates,
+ * when device memory allows, max_steps more buffers, into which each recorded step
+ * stores its pre-collision populations, so that the reverse sweep reads them
+ * instead of re-gathering them (4000 steps of the 199k-site half aneurysm in FP32:
+ * 96 GB in all); otherwise, and with 16-bit storage, only the states are kept, with
+ * the same results.  Every other call works as before; a
  * hemelb_lb_step request that would go past the record (nothing is done) and
  * hemelb_lb_set_state / _set_deviations during it return EORDER.
  * hemelb_lb_adjoint_recorded runs the reverse sweep (after hemelb_lb_adjoint_begin)

@@ -2215,19 +2215,29 @@ static int record_impl(hemelb_lb_t h, int64_t max_steps) {
     HIP_TRY(hipSetDevice(h->device), "set device");
     const size_t popbytes = (size_t)h->q * h->slots * h->elem();
     // max_steps + 1 states and, with FP32 storage and halfway walls, the pre-collision
-    // populations of each recorded step (with 16-bit storage the reverse step's
-    // re-gather is as fast as reading them, so they are not kept)
+    // populations of each recorded step when memory allows (with 16-bit storage the
+    // reverse step's re-gather is as fast as reading them, so they are not kept)
     std::vector<void*> rec, frec;
-    const int64_t nf = h->storage == HEMELB_STORE_F32 && !h->bfl ? max_steps : 0;
-    for (int64_t m = 0; m <= max_steps + nf; ++m) {
+    for (int64_t m = 0; m <= max_steps; ++m) {
         void* p = nullptr;
         const hipError_t e = hipMalloc(&p, popbytes);
         if (e != hipSuccess) {
             for (void* x : rec) (void)hipFree(x);
-            for (void* x : frec) (void)hipFree(x);
             return hip_fail(e, "trajectory record");
         }
-        (m <= max_steps ? rec : frec).push_back(p);
+        rec.push_back(p);
+    }
+    if (h->storage == HEMELB_STORE_F32 && !h->bfl) {
+        for (int64_t m = 0; m < max_steps; ++m) {
+            void* p = nullptr;
+            if (hipMalloc(&p, popbytes) != hipSuccess) {  // states only: the reverse re-gathers
+                (void)hipGetLastError();                  // leave no error for later calls
+                for (void* x : frec) (void)hipFree(x);
+                frec.clear();
+                break;
+            }
+            frec.push_back(p);
+        }
     }
     // the current state (with its ghost slots) starts the record
     HIP_TRY(hipMemcpyAsync(rec[0], h->A[h->cur], popbytes, hipMemcpyDeviceToDevice, h->stream),
