@@ -374,7 +374,8 @@ class LB:
         self._keep = keep
 
     def record(self, max_steps):
-        """Keep the next `max_steps` states on the device (hemelb_lb_record)."""
+        """Keep the next `max_steps` states on the device (hemelb_lb_record); with
+        FP32 storage also each step's pre-collision populations, when memory allows."""
         L.check(self.lib.hemelb_lb_record(self.h, int(max_steps)))
 
     def adjoint_recorded(self):
