@@ -17,8 +17,13 @@
 //  * two-level block addressing (4x4x4 blocks with fluid bitmaps): each 256-thread
 //    workgroup stages the block records its four tiles need into LDS with one
 //    coalesced load and decodes every link from LDS.
-// The work is a gather/scatter stencil at ~1.3 flop per byte, bound by HBM
-// bandwidth, so there is no matrix-core work.
+// The work is a gather stencil at ~1.3 flop per byte, memory-bound (in practice by
+// the rate of requests from L1 to L2 that the gathers issue), so there is no
+// matrix-core work.  With FP32 storage and block addressing, workgroups of 4 or 8
+// tiles first copy their own tiles' populations into LDS, by loads that write LDS
+// directly, and pulls from inside the workgroup read LDS: fewer L1 misses reach
+// L2.  A variant of the step also stores the pulled populations, for the reverse
+// sweep over a recorded trajectory.
 //
 // Memory layout: sites are Morton-ordered and grouped in tiles of 64, the width of
 // a wavefront.  Populations are stored [tile][direction][64] and the tables
